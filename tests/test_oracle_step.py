@@ -1,0 +1,183 @@
+"""Pins of the oracle's full split step (Eq. (17)) against facts fixed by the
+paper's tests and by kinetic theory: exact translation under free streaming at
+integer Courant numbers (Test 1), mass conservation, the linear growth and
+damping rates of the dispersion relation Eq. (38) (Test 2), Galilean
+invariance (Test 3), energy conservation and bitwise restart determinism."""
+import math
+
+import numpy as np
+import pytest
+from scipy import optimize, special
+
+from oracle import Grid, Run
+from paper_1206_6152_amd import inputs
+
+
+def grid_of(w):
+    return Grid(n=w.n, nv=w.nv, L=w.L, vmin=w.vmin, vmax=w.vmax, G=w.G, bc=w.bc)
+
+
+def growth_root(k_over_kj: float) -> float:
+    """y with k^2/k_J^2 = 1 + w Z(w) at w = i y (Eq. (38)); Z(w) = i sqrt(pi) wofz(w)."""
+    def h(y):
+        w = 1j * y
+        return (1 + w * 1j * math.sqrt(math.pi) * special.wofz(w)).real - k_over_kj ** 2
+    if k_over_kj < 1:
+        return optimize.brentq(h, 1e-9, 1e4, xtol=1e-14)
+    return optimize.brentq(h, -5.0, -1e-9, xtol=1e-14)
+
+
+def gamma_of(k_over_kj: float, G=1.0, rho=1.0) -> float:
+    # w = i gamma / (sqrt(8 pi G rho) k/k_J)  (Eq. (40))
+    return growth_root(k_over_kj) * math.sqrt(8 * math.pi * G * rho) * k_over_kj
+
+
+def test_dispersion_roots_known_limits():
+    # long-wavelength limit: gamma -> sqrt(4 pi G rho) (fluid Jeans rate)
+    assert gamma_of(1e-2) == pytest.approx(math.sqrt(4 * math.pi), rel=1e-3)
+    # marginal stability at k = k_J
+    assert abs(growth_root(0.999999)) < 1e-3
+    # damped for k > k_J
+    assert gamma_of(2.0) < 0
+
+
+def mode_amplitude(rho, m):
+    d = rho / rho.mean() - 1.0
+    n = d.shape[0]
+    x = np.arange(n)
+    return 2 * abs(np.mean(d[:, 0, 0] * np.exp(-2j * np.pi * m * x / n)))
+
+
+def test_free_streaming_integer_shift_full_step(orc):
+    # Test 1 set-up in 2D phase space (degenerate other axes), G = 0: the kicks
+    # are the identity and with dt = 2 dx / dv every velocity row moves by an
+    # odd integer number of cells, so one step is an exact periodic shift.
+    n, nv = 32, 16
+    w = inputs.one_d(n, nv, L=1.0, vbox=1.0, G=0.0)
+    g = grid_of(w)
+    f = np.zeros(w.shape)
+    x = w.xc(0)
+    v = w.vc(0)
+    f[:, 0, 0, :, 0, 0] = ((np.abs(x)[:, None] <= 0.25) & (np.abs(v)[None, :] <= 0.5)).astype(float)
+    dt = 2 * w.dx(0) / w.dv(0)
+    r = Run(g, f)
+    r.step(dt)
+    shift = np.rint(v * dt / w.dx(0)).astype(int)
+    ref = np.stack([np.roll(f[:, 0, 0, j, 0, 0], shift[j]) for j in range(nv)], axis=1)
+    assert np.array_equal(r.f[:, 0, 0, :, 0, 0], ref)
+
+
+def test_mass_conserved_without_velocity_outflow(orc):
+    # velocity box of +-9 sigma: the Maxwellian tail at the edge is ~1e-18 of
+    # the peak, so nothing measurable leaves and the mass is conserved to
+    # rounding (Sec. 2.1: the scheme conserves mass by construction)
+    w0 = inputs.landau_8_16()
+    vb = 9 * w0.params["sigma"]
+    w = inputs.Workload(name="landau_wide", n=(8, 8, 8), nv=(16, 16, 16), L=w0.L,
+                        vmin=(-vb,) * 3, vmax=(vb,) * 3, G=1.0, bc=0, dt=w0.dt, steps=3,
+                        params=w0.params)
+    g = grid_of(w)
+    f0 = inputs.initial_f(w)
+    r = Run(g, f0)
+    m0 = orc.energy(g, r.f)[2]
+    for _ in range(3):
+        r.step(w.dt)
+    m1 = orc.energy(g, r.f)[2]
+    assert abs(m1 - m0) / m0 < 1e-11  # rounding of ~2e6 cells over 27 sweeps
+
+
+def _run_1d(k_over_kj, amp, nx, nv, vbox_sigmas, t_end, drift=0.0, cfl=0.5, dt=None):
+    k = 2 * (2 * math.pi)                   # k = 2 k0 with L = 1 (Sec. 3.2)
+    s = inputs.jeans_sigma(k_over_kj, k)
+    vbox = vbox_sigmas * s if vbox_sigmas else 1.0
+    w = inputs.one_d(nx, nv, L=1.0, vbox=vbox + abs(drift))
+    g = grid_of(w)
+    dens = inputs.cosine_density(w, 1.0, amp, mode=(2, 0, 0))
+    m = inputs.maxwellian(w, s, drift=(drift, 0, 0))
+    f0 = dens.reshape(w.n + (1, 1, 1)) * m.reshape((1, 1, 1) + w.nv)
+    import oracle
+    r = Run(g, f0)
+    if dt is None:
+        dt = oracle.dt(g, r.a, cfl)
+    ts, amps, en = [0.0], [mode_amplitude(oracle.density(g, r.f), 2)], [oracle.energy(g, r.f)]
+    t = 0.0
+    while t < t_end - 1e-12:
+        r.step(dt)
+        t += dt
+        ts.append(t)
+        amps.append(mode_amplitude(oracle.density(g, r.f), 2))
+    en.append(oracle.energy(g, r.f))
+    return np.array(ts), np.array(amps), en
+
+
+def test_jeans_growth_rate_matches_linear_theory(orc):
+    # Test 2, k/k_J = 0.5: |A_2| grows at the rate of Eq. (38) in the early phase.
+    ts, amps, en = _run_1d(0.5, 0.01, 64, 128, None, 1.0)
+    gam = gamma_of(0.5)
+    model = lambda t, a, b, g_: np.log(np.abs(a * np.exp(g_ * t) + b * np.exp(-g_ * t)))
+    popt, _ = optimize.curve_fit(model, ts, np.log(amps), p0=[0.005, 0.005, 2.0])
+    assert popt[2] == pytest.approx(gam, rel=0.08), (popt, gam)
+    # mass and energy (Sec. 3.2: 1e-6 and 1e-3)
+    (K0, U0, M0, E0), (K1, U1, M1, E1) = en
+    assert abs(M1 - M0) / M0 < 1e-6
+    assert abs(E1 - E0) / abs(K0) < 1e-3
+
+
+def test_landau_damping_rate_sign_and_size(orc):
+    # Test 2, k/k_J = 2: the mode decays; the late-time decay rate is of the
+    # size Eq. (38) gives (the paper notes departures at late times).
+    ts, amps, _ = _run_1d(2.0, 0.1, 64, 128, 5.0, 0.35)
+    gam = gamma_of(2.0)
+    assert amps[-1] < 0.2 * amps[0]
+    sel = (ts > 0.12) & (ts < 0.3)
+    rate = np.polyfit(ts[sel], np.log(amps[sel]), 1)[0]
+    assert rate == pytest.approx(gam, rel=0.3), (rate, gam)
+
+
+def test_galilean_invariance(orc):
+    # Test 3: a uniform drift v_t = sigma leaves |A_2(t)| unchanged up to
+    # discretisation error.
+    s = inputs.jeans_sigma(0.5, 4 * math.pi)
+    dt = 0.5 * (1.0 / 64) / (7 * s)
+    ts0, a0, _ = _run_1d(0.5, 0.01, 64, 128, 6.0, 0.5, dt=dt)
+    ts1, a1, _ = _run_1d(0.5, 0.01, 64, 128, 6.0, 0.5, drift=s, dt=dt)
+    assert a0[-1] > 1.5 * a0[0]
+    np.testing.assert_allclose(a1, a0, rtol=0.03)
+
+
+def test_restart_is_bitwise_deterministic(orc):
+    w = inputs.landau_8_16().with_grid(n=(4, 4, 4), nv=(8, 8, 8))
+    g = grid_of(w)
+    f0 = inputs.initial_f(w)
+    a = Run(g, f0)
+    for _ in range(4):
+        a.step(w.dt)
+    b = Run(g, f0)
+    for _ in range(2):
+        b.step(w.dt)
+    c = Run(g, b.f.copy(), b.a.copy())
+    for _ in range(2):
+        c.step(w.dt)
+    assert np.array_equal(a.f, c.f)
+    assert np.array_equal(a.a, c.a)
+
+
+def test_step_is_the_operator_product(orc):
+    # Eq. (17) written out with individual sweeps and the Poisson solve placed
+    # after the position sweeps (force reuse for the first half kick)
+    w = inputs.landau_8_16().with_grid(n=(4, 4, 4), nv=(6, 6, 6))
+    g = grid_of(w)
+    f0 = inputs.initial_f(w)
+    r = Run(g, f0)
+    a0 = r.a.copy()
+    r.step(w.dt)
+    f = f0.copy()
+    for ax in (3, 4, 5):
+        f = orc.sweep(g, f, ax, w.dt / 2, a0)
+    for ax in (2, 1, 0):
+        f = orc.sweep(g, f, ax, w.dt)
+    a1 = orc.accel(g, f)
+    for ax in (3, 4, 5):
+        f = orc.sweep(g, f, ax, w.dt / 2, a1)
+    assert np.array_equal(f, r.f)
+    assert np.array_equal(a1, r.a)
