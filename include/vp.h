@@ -1,0 +1,150 @@
+/*
+ * vp.h -- C ABI of the MI355X (gfx950) six-dimensional Vlasov-Poisson library.
+ *
+ * The library advances a distribution function f(x, y, z, vx, vy, vz) of a
+ * collisionless self-gravitating system with the directionally split
+ * positive-flux-conservative (PFC) scheme of Yoshikawa, Yoshida & Umemura
+ * (arXiv:1206.6152), Sec. 2: one-dimensional PFC advections along each phase-
+ * space axis (Sec. 2.1, Eqs. (5)-(16)), composed as the leapfrog product of
+ * Eq. (17), with the density of Eq. (18), the FFT-convolution Poisson solve of
+ * Sec. 2.2 (periodic, Eqs. (19)-(20); isolated by grid doubling, Eq. (21)) and
+ * the two-point acceleration of Eq. (22).
+ *
+ * Conventions shared by every entry point
+ *   - Grid (Sec. 2, Eqs. (3)-(4)): space is [-L/2, L/2) per axis with cell
+ *     centres x_i = -L/2 + (i + 1/2) L/N; velocity is [vmin, vmax] per axis
+ *     with centres v_j = vmin + (j + 1/2) dv, dv = (vmax - vmin)/Nv.
+ *   - f layout: one C-order array f[Nx][Ny][Nz][Nvx][Nvy][Nvz] (vz fastest)
+ *     of float (VP_F32) or double (VP_F64) in device memory. The element type
+ *     is the storage and sweep precision; density, potential, acceleration and
+ *     diagnostics are always FP64.
+ *   - Spatial fields (rho, accel components) are C-order [Nx][Ny][Nz] FP64.
+ *     The potential is returned with one ghost layer, [Nx+2][Ny+2][Nz+2]
+ *     (index 0 holds cell -1).
+ *   - Every call returns 0 (VP_OK) or a negative VP_E* code; vp_last_error()
+ *     then describes the failure. Arguments are validated before any device
+ *     work, so VP_EINVAL leaves the state untouched.
+ *   - Work is enqueued asynchronously on the HIP stream given to vp_init.
+ *     Only vp_energy and vp_dt wait for the stream (they return host values).
+ *   - The library is not re-entrant per context: calls on one context must
+ *     not overlap. Distinct contexts are independent.
+ *
+ * Boundary conditions (Sec. 2.1): velocity axes are always outflow (matter
+ * pushed past vmin/vmax is lost). VP_BC_PERIODIC makes the spatial sweeps and
+ * the Poisson solve periodic; VP_BC_ISOLATED makes the spatial sweeps outflow
+ * and the Poisson solve isolated.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VP_OK 0
+#define VP_EINVAL (-1)        /* bad argument or configuration */
+#define VP_ENOMEM (-2)        /* device allocation failed */
+#define VP_EHIP (-3)          /* HIP runtime or kernel launch failure */
+#define VP_ENONFINITE (-4)    /* a diagnostic sum is not finite */
+#define VP_EUNSUPPORTED (-5)  /* valid request this build does not implement */
+
+#define VP_BC_PERIODIC 0
+#define VP_BC_ISOLATED 1
+
+#define VP_F32 0
+#define VP_F64 1
+
+/* Problem statement of Sec. 2. All lengths >= 1. Every one of the six axis
+ * lengths must be one of the line lengths the sweep kernels are built for:
+ * 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128. VP_BC_ISOLATED needs
+ * equal spacings dx = dy = dz. */
+typedef struct vp_config {
+  int32_t n[3];       /* spatial cells Nx, Ny, Nz */
+  int32_t nv[3];      /* velocity cells Nvx, Nvy, Nvz */
+  double L[3];        /* box lengths (> 0) */
+  double vmin[3];     /* V^- per axis */
+  double vmax[3];     /* V^+ per axis (> vmin) */
+  double G;           /* gravitational constant (>= 0) */
+  int32_t bc;         /* VP_BC_PERIODIC or VP_BC_ISOLATED */
+  int32_t dtype;      /* VP_F32 or VP_F64: element type of f */
+  int32_t flags;      /* must be 0 */
+  int32_t reserved;   /* must be 0 */
+} vp_config;
+
+typedef struct vp_ctx vp_ctx;  /* opaque */
+
+/* sizeof(vp_config) as compiled into the library (binding self-check). */
+int vp_config_size(void);
+
+/* Pure host validation of a configuration; touches no device. */
+int vp_config_validate(const vp_config* cfg);
+
+/* Create a context on the current HIP device for the f array at f_dev (device
+ * pointer, layout and type above, caller-owned). The library BORROWS f: it
+ * updates it in place and the caller keeps it alive, and does not modify it
+ * behind the library's back, until vp_free. hip_stream is a hipStream_t (NULL
+ * for the null stream). Allocates the FP64 work fields and computes the
+ * initial acceleration from f (density, Poisson, gradient). On success *out
+ * receives the context; on failure *out is NULL and nothing stays allocated. */
+int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out);
+
+/* One step of Eq. (17): T_vx, T_vy, T_vz at dt/2 with the current
+ * acceleration; T_z, T_y, T_x at dt; density, Poisson solve and acceleration;
+ * T_vx, T_vy, T_vz at dt/2 with the new acceleration. The acceleration left in
+ * the context serves the first half kick of the next step, so the Poisson
+ * equation is solved once per step, after the position sweeps as the paper
+ * states. dt must be finite and > 0. */
+int vp_step(vp_ctx* ctx, double dt);
+
+/* n consecutive vp_step calls with the same dt (n >= 0). */
+int vp_run(vp_ctx* ctx, int32_t nsteps, double dt);
+
+/* A single one-dimensional PFC advection T_axis(tau) of every line of f
+ * (Sec. 2.1, Eqs. (11)-(16)): axis 0, 1, 2 = x, y, z move with the cell's
+ * velocity v_axis; axis 3, 4, 5 = vx, vy, vz move with the stored
+ * acceleration a_{axis-3} of the spatial cell. tau must be finite (any sign;
+ * any Courant number). */
+int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
+
+/* Recompute the stored acceleration from the current f (Eqs. (18)-(22)). */
+int vp_accel(vp_ctx* ctx);
+
+/* Copy the stored acceleration to a_dev ([3][Nx][Ny][Nz] FP64, device), or
+ * replace it from a_dev. */
+int vp_get_accel(vp_ctx* ctx, double* a_dev);
+int vp_set_accel(vp_ctx* ctx, const double* a_dev);
+
+/* rho = integral of f over velocity (Eq. (18)) of the current f, written to
+ * rho_dev ([Nx][Ny][Nz] FP64, device, caller-owned). Asynchronous. */
+int vp_density(vp_ctx* ctx, double* rho_dev);
+
+/* Potential of the current f (Eqs. (18)-(21)) with one ghost layer, written to
+ * phi_dev ([Nx+2][Ny+2][Nz+2] FP64, device, caller-owned). Periodic: the
+ * k = 0 mode is zero and ghosts are periodic images. Isolated: ghosts hold
+ * the convolution evaluated one cell outside the box. Asynchronous. */
+int vp_potential(vp_ctx* ctx, double* phi_dev);
+
+/* Kinetic, potential and total energy and mass of the current f
+ * (Eqs. (29), (30), (41)), out_host[0..3] = K, U, M, E, with cell-centre
+ * velocities. Synchronises the stream. VP_ENONFINITE if a sum is not finite. */
+int vp_energy(vp_ctx* ctx, double out_host[4]);
+
+/* dt = cfl * min(dt_p, dt_v) of Eqs. (23)-(25) from the stored acceleration,
+ * with V^max = max(|vmin|, |vmax|) per axis; an axis with no velocity extent
+ * or no acceleration imposes no limit. Synchronises the stream. */
+int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
+
+/* Release everything the context owns (never f). NULL is accepted. */
+int vp_free(vp_ctx* ctx);
+
+/* Description of the last failure on the calling thread ("" if none); valid
+ * until the next vp_* call on the thread. */
+const char* vp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

@@ -1,0 +1,373 @@
+// gravity.hip -- density moment, Fourier-convolution Poisson solve, two-point
+// acceleration and FP64 reductions (Sec. 2.2 and Eqs. (18)-(25), (29), (30),
+// (41) of Yoshikawa, Yoshida & Umemura) for gfx950.
+//
+// The transforms are discrete Fourier transforms done axis by axis: one
+// workgroup takes one line, stages it and the twiddle table in LDS, and every
+// lane produces output frequencies. The spatial grids of this method are small
+// (at most a few hundred cells per axis), and the Poisson solve is a small
+// fraction of a step, so a direct per-line transform is used instead of a
+// general FFT library. All of it runs in FP64.
+#include "vp_internal.h"
+
+namespace vp {
+namespace {
+
+constexpr int RED = 256;  // reduction workgroup size
+
+__device__ __forceinline__ double block_sum(double x, double* sh)
+{
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = RED / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double x, double* sh)
+{
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = RED / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// rho = dv3 * sum over the contiguous velocity block of one spatial cell
+template <typename T>
+__global__ __launch_bounds__(RED) void density_kernel(const T* f, double* rho, long long nv3, double dv3)
+{
+  __shared__ double sh[RED];
+  const T* p = f + (long long)blockIdx.x * nv3;
+  double acc = 0.0;
+  for (long long j = threadIdx.x; j < nv3; j += RED) acc += (double)p[j];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) rho[blockIdx.x] = s * dv3;
+}
+
+__global__ void twiddle_kernel(double2* w, int M)
+{
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double sn, cs;
+  sincospi(2.0 * (double)k / (double)M, &sn, &cs);
+  w[k] = make_double2(cs, -sn);  // exp(-2 pi i k / M)
+}
+
+// One workgroup per line of the axis; lanes compute frequencies.
+__global__ __launch_bounds__(128) void dft_kernel(double2* data, long long inner, int M, int sign,
+                                                   const double2* tw)
+{
+  extern __shared__ double2 lds[];
+  double2* x = lds;       // M values
+  double2* w = lds + M;   // M twiddles
+  const long long line = blockIdx.x;
+  const long long o = line / inner;
+  const long long c = line - o * inner;
+  double2* p = data + o * (long long)M * inner + c;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    x[j] = p[(long long)j * inner];
+    const double2 t = tw[j];
+    w[j] = make_double2(t.x, sign < 0 ? t.y : -t.y);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < M; k += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    int idx = 0;  // (j * k) mod M
+    for (int j = 0; j < M; j++) {
+      const double2 a = x[j];
+      const double2 b = w[idx];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+      idx += k;
+      if (idx >= M) idx -= M;
+    }
+    p[(long long)k * inner] = make_double2(sr, si);
+  }
+}
+
+__global__ void load_rho_kernel(double2* data, Grid3 g, const double* rho, Grid3 n)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < tot;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int i2 = (int)(s % g.m[2]);
+    const int i1 = (int)((s / g.m[2]) % g.m[1]);
+    const int i0 = (int)(s / ((long long)g.m[2] * g.m[1]));
+    double v = 0.0;
+    if (i0 < n.m[0] && i1 < n.m[1] && i2 < n.m[2]) v = rho[((long long)i0 * n.m[1] + i1) * n.m[2] + i2];
+    data[s] = make_double2(v, 0.0);
+  }
+}
+
+// G_hat(k) = -pi G / sum_l sin^2(pi k_l / M_l) / d_l^2 (Eq. (20), unequal
+// spacings), zero at k = 0.
+__global__ void green_periodic_kernel(double2* data, Grid3 g, double G, double d0, double d1, double d2)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  const double pi = 3.14159265358979323846;
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < tot;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int k2 = (int)(s % g.m[2]);
+    const int k1 = (int)((s / g.m[2]) % g.m[1]);
+    const int k0 = (int)(s / ((long long)g.m[2] * g.m[1]));
+    const double s0 = sinpi((double)k0 / g.m[0]);
+    const double s1 = sinpi((double)k1 / g.m[1]);
+    const double s2 = sinpi((double)k2 / g.m[2]);
+    const double den = s0 * s0 / (d0 * d0) + s1 * s1 / (d1 * d1) + s2 * s2 / (d2 * d2);
+    const double gk = (k0 == 0 && k1 == 0 && k2 == 0) ? 0.0 : -pi * G / den;
+    const double2 v = data[s];
+    data[s] = make_double2(v.x * gk, v.y * gk);
+  }
+}
+
+__global__ void mul_spectrum_kernel(double2* data, const double2* spec, long long count)
+{
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < count;
+       s += (long long)gridDim.x * blockDim.x) {
+    const double2 a = data[s], b = spec[s];
+    data[s] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  }
+}
+
+// Isolated Green's function of the doubled grid: K(r) = -G d0 d1 d2 / |r| at
+// the mirrored offset, self_value at the origin.
+__global__ void green_isolated_kernel(double2* data, Grid3 g, double G, double d0, double d1, double d2,
+                                      double self_value)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < tot;
+       s += (long long)gridDim.x * blockDim.x) {
+    int o2 = (int)(s % g.m[2]);
+    int o1 = (int)((s / g.m[2]) % g.m[1]);
+    int o0 = (int)(s / ((long long)g.m[2] * g.m[1]));
+    o0 = min(o0, g.m[0] - o0);
+    o1 = min(o1, g.m[1] - o1);
+    o2 = min(o2, g.m[2] - o2);
+    double v;
+    if (o0 == 0 && o1 == 0 && o2 == 0) {
+      v = self_value;
+    } else {
+      const double x = o0 * d0, y = o1 * d1, z = o2 * d2;
+      v = -G * d0 * d1 * d2 / sqrt(x * x + y * y + z * z);
+    }
+    data[s] = make_double2(v, 0.0);
+  }
+}
+
+__global__ void extract_phi_kernel(double* phi, Grid3 n, const double2* data, Grid3 g, double scale)
+{
+  const int e0 = n.m[0] + 2, e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  const long long tot = (long long)e0 * e1 * e2;
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < tot;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int t2 = (int)(s % e2) - 1;
+    const int t1 = (int)((s / e2) % e1) - 1;
+    const int t0 = (int)(s / ((long long)e2 * e1)) - 1;
+    const int w0 = (t0 + g.m[0]) % g.m[0];
+    const int w1 = (t1 + g.m[1]) % g.m[1];
+    const int w2 = (t2 + g.m[2]) % g.m[2];
+    phi[s] = data[((long long)w0 * g.m[1] + w1) * g.m[2] + w2].x * scale;
+  }
+}
+
+__global__ void gradient_kernel(double* a, const double* phi, Grid3 n, double d0, double d1, double d2)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < np;
+       s += (long long)gridDim.x * blockDim.x) {
+    const long long i2 = s % n.m[2];
+    const long long i1 = (s / n.m[2]) % n.m[1];
+    const long long i0 = s / ((long long)n.m[2] * n.m[1]);
+    const long long c = ((i0 + 1) * e1 + (i1 + 1)) * e2 + (i2 + 1);
+    a[s] = -(phi[c + e1 * e2] - phi[c - e1 * e2]) / (2.0 * d0);
+    a[np + s] = -(phi[c + e2] - phi[c - e2]) / (2.0 * d1);
+    a[2 * np + s] = -(phi[c + 1] - phi[c - 1]) / (2.0 * d2);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RED) void energy_partial_kernel(const T* f, double* part, VelGrid vg)
+{
+  __shared__ double sh[RED];
+  const long long nv3 = (long long)vg.nv[0] * vg.nv[1] * vg.nv[2];
+  const T* p = f + (long long)blockIdx.x * nv3;
+  double m = 0.0, k = 0.0;
+  for (long long j = threadIdx.x; j < nv3; j += RED) {
+    const int jz = (int)(j % vg.nv[2]);
+    const int jy = (int)((j / vg.nv[2]) % vg.nv[1]);
+    const int jx = (int)(j / ((long long)vg.nv[2] * vg.nv[1]));
+    const double vx = vg.vmin[0] + (jx + 0.5) * vg.dv[0];
+    const double vy = vg.vmin[1] + (jy + 0.5) * vg.dv[1];
+    const double vz = vg.vmin[2] + (jz + 0.5) * vg.dv[2];
+    const double x = (double)p[j];
+    m += x;
+    k += x * (vx * vx + vy * vy + vz * vz);
+  }
+  const double ms = block_sum(m, sh);
+  const double ks = block_sum(k, sh);
+  if (threadIdx.x == 0) {
+    part[2 * (long long)blockIdx.x] = ms;
+    part[2 * (long long)blockIdx.x + 1] = ks;
+  }
+}
+
+__global__ __launch_bounds__(RED) void energy_final_kernel(double* out, const double* part, const double* rho,
+                                                           const double* phi, Grid3 n, double dx3, double dv3)
+{
+  __shared__ double sh[RED];
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  double m = 0.0, k = 0.0, u = 0.0;
+  for (long long s = threadIdx.x; s < np; s += RED) {
+    m += part[2 * s];
+    k += part[2 * s + 1];
+    const long long i2 = s % n.m[2];
+    const long long i1 = (s / n.m[2]) % n.m[1];
+    const long long i0 = s / ((long long)n.m[2] * n.m[1]);
+    u += rho[s] * phi[((i0 + 1) * e1 + (i1 + 1)) * e2 + (i2 + 1)];
+  }
+  const double ms = block_sum(m, sh);
+  const double ks = block_sum(k, sh);
+  const double us = block_sum(u, sh);
+  if (threadIdx.x == 0) {
+    const double K = 0.5 * ks * dx3 * dv3;
+    const double U = 0.5 * us * dx3;
+    out[0] = K;
+    out[1] = U;
+    out[2] = ms * dx3 * dv3;
+    out[3] = K + U;
+  }
+}
+
+__global__ __launch_bounds__(RED) void accel_max_kernel(double* out, const double* a, long long np, double i0,
+                                                        double i1, double i2)
+{
+  __shared__ double sh[RED];
+  double m = 0.0;
+  for (long long s = threadIdx.x; s < np; s += RED) {
+    m = fmax(m, fabs(a[s]) * i0);
+    m = fmax(m, fabs(a[np + s]) * i1);
+    m = fmax(m, fabs(a[2 * np + s]) * i2);
+  }
+  const double r = block_max(m, sh);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+unsigned grid_for(long long n, int block)
+{
+  long long b = (n + block - 1) / block;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_density(const void* f, int dtype, double* rho, long long np, long long nv3, double dv3,
+                          hipStream_t s)
+{
+  if (dtype == 0)
+    hipLaunchKernelGGL(density_kernel<float>, dim3((unsigned)np), dim3(RED), 0, s, (const float*)f, rho, nv3, dv3);
+  else
+    hipLaunchKernelGGL(density_kernel<double>, dim3((unsigned)np), dim3(RED), 0, s, (const double*)f, rho, nv3, dv3);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(double2* w, int M, hipStream_t s)
+{
+  hipLaunchKernelGGL(twiddle_kernel, dim3((M + 127) / 128), dim3(128), 0, s, w, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_axis(double2* data, Grid3 g, int axis, int sign, const double2* tw, hipStream_t s)
+{
+  long long inner = 1;
+  for (int q = 2; q > axis; q--) inner *= g.m[q];
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  const int M = g.m[axis];
+  const long long lines = tot / M;
+  if (M == 1) return hipSuccess;
+  const size_t lds = 2 * (size_t)M * sizeof(double2);
+  hipLaunchKernelGGL(dft_kernel, dim3((unsigned)lines), dim3(128), lds, s, data, inner, M, sign, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_rho(double2* data, Grid3 g, const double* rho, Grid3 n, hipStream_t s)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  hipLaunchKernelGGL(load_rho_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, data, g, rho, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_green_periodic(double2* data, Grid3 g, double G, double d0, double d1, double d2, hipStream_t s)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  hipLaunchKernelGGL(green_periodic_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, data, g, G, d0, d1, d2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul_spectrum(double2* data, const double2* spec, long long count, hipStream_t s)
+{
+  hipLaunchKernelGGL(mul_spectrum_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, data, spec, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_green_isolated(double2* data, Grid3 g, double G, double d0, double d1, double d2,
+                                 double self_value, hipStream_t s)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  hipLaunchKernelGGL(green_isolated_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, data, g, G, d0, d1, d2,
+                     self_value);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_phi(double* phi_ext, Grid3 n, const double2* data, Grid3 g, double scale, hipStream_t s)
+{
+  const long long tot = (long long)(n.m[0] + 2) * (n.m[1] + 2) * (n.m[2] + 2);
+  hipLaunchKernelGGL(extract_phi_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, phi_ext, n, data, g, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient(double* accel, const double* phi_ext, Grid3 n, double d0, double d1, double d2,
+                           hipStream_t s)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  hipLaunchKernelGGL(gradient_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, accel, phi_ext, n, d0, d1, d2);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_partials(const void* f, int dtype, double* part, long long np, VelGrid vg, hipStream_t s)
+{
+  if (dtype == 0)
+    hipLaunchKernelGGL(energy_partial_kernel<float>, dim3((unsigned)np), dim3(RED), 0, s, (const float*)f, part, vg);
+  else
+    hipLaunchKernelGGL(energy_partial_kernel<double>, dim3((unsigned)np), dim3(RED), 0, s, (const double*)f, part,
+                       vg);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_final(double* out, const double* part, const double* rho, const double* phi_ext, Grid3 n,
+                               double dx3, double dv3, hipStream_t s)
+{
+  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(RED), 0, s, out, part, rho, phi_ext, n, dx3, dv3);
+  return hipGetLastError();
+}
+
+hipError_t launch_accel_max(double* out, const double* accel, long long np, double i0, double i1, double i2,
+                            hipStream_t s)
+{
+  hipLaunchKernelGGL(accel_max_kernel, dim3(1), dim3(RED), 0, s, out, accel, np, i0, i1, i2);
+  return hipGetLastError();
+}
+
+}  // namespace vp

@@ -1,0 +1,453 @@
+// vp_api.hip -- host side of the C ABI declared in include/vp.h: configuration
+// checks, the context and its FP64 work fields, and the sequencing of the
+// kernels of one step of Eq. (17) (Yoshikawa, Yoshida & Umemura, Sec. 2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "vp.h"
+#include "vp_internal.h"
+
+using vp::Grid3;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+bool debug_sync()
+{
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("VP_DEBUG_SYNC");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+}  // namespace
+
+struct vp_ctx {
+  vp_config cfg;
+  void* f = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  long long np = 0, nv3 = 0;
+  double dx[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+  Grid3 ng{};           // spatial grid
+  Grid3 wg{};           // transform grid: ng (periodic) or 2 ng (isolated)
+  double* rho = nullptr;
+  double* phi = nullptr;      // (N+2)^3
+  double* accel = nullptr;    // [3][np]
+  double2* work = nullptr;    // wg cells
+  double2* kspec = nullptr;   // isolated Green's function spectrum
+  double2* tw[3] = {nullptr, nullptr, nullptr};
+  double* part = nullptr;     // 2 * np
+  double* red = nullptr;      // 8 doubles on the device
+  double* host = nullptr;     // 8 pinned doubles
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(VP_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+int check_launch(vp_ctx* c, hipError_t e, const char* what)
+{
+  if (e != hipSuccess) return fail(VP_EHIP, "%s: %s", what, hipGetErrorString(e));
+  if (debug_sync()) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(VP_EHIP, "%s (sync): %s", what, hipGetErrorString(e));
+  }
+  return VP_OK;
+}
+
+#define LAUNCH(c, expr)                                 \
+  do {                                                  \
+    int r_ = check_launch((c), (expr), #expr);          \
+    if (r_ != VP_OK) return r_;                         \
+  } while (0)
+
+// Integral of 1/|r| over [0,a]x[0,b]x[0,c] (closed form for the potential of a
+// uniform box at a corner); eight of them give the cell self term.
+double corner_integral(double a, double b, double c)
+{
+  const double d = std::sqrt(a * a + b * b + c * c);
+  return a * b * std::log((c + d) / std::sqrt(a * a + b * b)) +
+         b * c * std::log((a + d) / std::sqrt(b * b + c * c)) +
+         c * a * std::log((b + d) / std::sqrt(c * c + a * a)) -
+         0.5 * a * a * std::atan(b * c / (a * d)) - 0.5 * b * b * std::atan(c * a / (b * d)) -
+         0.5 * c * c * std::atan(a * b / (c * d));
+}
+
+void release(vp_ctx* c)
+{
+  if (!c) return;
+  hipFree(c->rho);
+  hipFree(c->phi);
+  hipFree(c->accel);
+  hipFree(c->work);
+  hipFree(c->kspec);
+  for (auto& t : c->tw) hipFree(t);
+  hipFree(c->part);
+  hipFree(c->red);
+  if (c->host) hipHostFree(c->host);
+  delete c;
+}
+
+template <typename P>
+int dalloc(P** p, size_t bytes, const char* what)
+{
+  hipError_t e = hipMalloc((void**)p, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    hipGetLastError();
+    return fail(VP_ENOMEM, "hipMalloc(%s, %zu bytes): %s", what, bytes, hipGetErrorString(e));
+  }
+  return VP_OK;
+}
+
+long long prod3(const int m[3]) { return (long long)m[0] * m[1] * m[2]; }
+
+// density -> rho, Poisson -> phi (with ghosts)
+int potential_into(vp_ctx* c, double* phi_out)
+{
+  const bool iso = c->cfg.bc == VP_BC_ISOLATED;
+  LAUNCH(c, vp::launch_density(c->f, c->cfg.dtype, c->rho, c->np, c->nv3,
+                               c->dv[0] * c->dv[1] * c->dv[2], c->stream));
+  LAUNCH(c, vp::launch_load_rho(c->work, c->wg, c->rho, c->ng, c->stream));
+  for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, -1, c->tw[ax], c->stream));
+  if (iso)
+    LAUNCH(c, vp::launch_mul_spectrum(c->work, c->kspec, prod3(c->wg.m), c->stream));
+  else
+    LAUNCH(c, vp::launch_green_periodic(c->work, c->wg, c->cfg.G, c->dx[0], c->dx[1], c->dx[2], c->stream));
+  for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, +1, c->tw[ax], c->stream));
+  LAUNCH(c, vp::launch_extract_phi(phi_out, c->ng, c->work, c->wg, 1.0 / (double)prod3(c->wg.m), c->stream));
+  return VP_OK;
+}
+
+int compute_accel(vp_ctx* c)
+{
+  int r = potential_into(c, c->phi);
+  if (r != VP_OK) return r;
+  LAUNCH(c, vp::launch_gradient(c->accel, c->phi, c->ng, c->dx[0], c->dx[1], c->dx[2], c->stream));
+  return VP_OK;
+}
+
+int sweep(vp_ctx* c, int axis, double tau)
+{
+  const auto& k = c->cfg;
+  long long d[6] = {k.n[0], k.n[1], k.n[2], k.nv[0], k.nv[1], k.nv[2]};
+  vp::SweepArgs a{};
+  a.f = c->f;
+  a.n = (int)d[axis];
+  a.inner = 1;
+  for (int q = 5; q > axis; q--) a.inner *= d[q];
+  a.outer = 1;
+  for (int q = 0; q < axis; q++) a.outer *= d[q];
+  a.nlines = a.outer * a.inner;
+  if (axis >= 3) {
+    const int l = axis - 3;
+    a.velocity = 1;
+    a.periodic = 0;
+    a.accel = c->accel + (long long)l * c->np;
+    a.scale = tau / c->dv[l];
+    a.sp_div = 1;
+    for (int q = 3; q < axis; q++) a.sp_div *= d[q];
+    a.j_div = 1;
+    a.j_mod = 1;
+  } else {
+    a.velocity = 0;
+    a.periodic = (k.bc == VP_BC_PERIODIC) ? 1 : 0;
+    a.scale = tau / c->dx[axis];
+    a.j_div = 1;
+    for (int q = 5; q > axis + 3; q--) a.j_div *= d[q];
+    a.j_mod = d[axis + 3];
+    a.vmin = k.vmin[axis];
+    a.dv = c->dv[axis];
+    a.sp_div = 1;
+  }
+  LAUNCH(c, vp::launch_sweep(a, k.dtype, c->stream));
+  return VP_OK;
+}
+
+int check_ctx(vp_ctx* c)
+{
+  if (!c) return fail(VP_EINVAL, "null context");
+  return VP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vp_config_size(void) { return (int)sizeof(vp_config); }
+
+int vp_config_validate(const vp_config* cfg)
+{
+  g_err.clear();
+  if (!cfg) return fail(VP_EINVAL, "null config");
+  for (int l = 0; l < 3; l++) {
+    if (cfg->n[l] < 1 || cfg->nv[l] < 1) return fail(VP_EINVAL, "axis %d: cell counts must be >= 1", l);
+    if (!vp::sweep_length_supported(cfg->n[l]))
+      return fail(VP_EUNSUPPORTED, "n[%d] = %d is not a supported line length", l, cfg->n[l]);
+    if (!vp::sweep_length_supported(cfg->nv[l]))
+      return fail(VP_EUNSUPPORTED, "nv[%d] = %d is not a supported line length", l, cfg->nv[l]);
+    if (!(std::isfinite(cfg->L[l]) && cfg->L[l] > 0)) return fail(VP_EINVAL, "L[%d] must be finite and > 0", l);
+    if (!(std::isfinite(cfg->vmin[l]) && std::isfinite(cfg->vmax[l]) && cfg->vmax[l] > cfg->vmin[l]))
+      return fail(VP_EINVAL, "velocity range of axis %d must be finite with vmax > vmin", l);
+  }
+  if (!(std::isfinite(cfg->G) && cfg->G >= 0)) return fail(VP_EINVAL, "G must be finite and >= 0");
+  if (cfg->bc != VP_BC_PERIODIC && cfg->bc != VP_BC_ISOLATED) return fail(VP_EINVAL, "unknown bc %d", cfg->bc);
+  if (cfg->dtype != VP_F32 && cfg->dtype != VP_F64) return fail(VP_EINVAL, "unknown dtype %d", cfg->dtype);
+  if (cfg->flags != 0 || cfg->reserved != 0) return fail(VP_EINVAL, "flags and reserved must be 0");
+  const double np = (double)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  const double nv = (double)cfg->nv[0] * cfg->nv[1] * cfg->nv[2];
+  if (np * nv > 9.0e18 / 8) return fail(VP_EINVAL, "grid too large");
+  if (np > 2.0e9 || nv > 2.0e9) return fail(VP_EINVAL, "spatial or velocity grid too large");
+  if (cfg->bc == VP_BC_ISOLATED) {
+    const double d0 = cfg->L[0] / cfg->n[0], d1 = cfg->L[1] / cfg->n[1], d2 = cfg->L[2] / cfg->n[2];
+    if (std::fabs(d0 - d1) > 1e-12 * d0 || std::fabs(d0 - d2) > 1e-12 * d0)
+      return fail(VP_EUNSUPPORTED, "isolated Poisson needs equal spacings");
+  }
+  return VP_OK;
+}
+
+int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
+{
+  g_err.clear();
+  if (!out) return fail(VP_EINVAL, "null output pointer");
+  *out = nullptr;
+  int r = vp_config_validate(cfg);
+  if (r != VP_OK) return r;
+  if (!f_dev) return fail(VP_EINVAL, "null f pointer");
+  vp_ctx* c = new (std::nothrow) vp_ctx;
+  if (!c) return fail(VP_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->f = f_dev;
+  c->stream = (hipStream_t)hip_stream;
+  hipGetDevice(&c->device);
+  for (int l = 0; l < 3; l++) {
+    c->dx[l] = cfg->L[l] / cfg->n[l];
+    c->dv[l] = (cfg->vmax[l] - cfg->vmin[l]) / cfg->nv[l];
+    c->ng.m[l] = cfg->n[l];
+    c->wg.m[l] = cfg->bc == VP_BC_ISOLATED ? 2 * cfg->n[l] : cfg->n[l];
+  }
+  c->np = prod3(c->ng.m);
+  c->nv3 = (long long)cfg->nv[0] * cfg->nv[1] * cfg->nv[2];
+  const long long ext = (long long)(cfg->n[0] + 2) * (cfg->n[1] + 2) * (cfg->n[2] + 2);
+  const long long wn = prod3(c->wg.m);
+  if ((r = dalloc(&c->rho, sizeof(double) * c->np, "rho")) ||
+      (r = dalloc(&c->phi, sizeof(double) * ext, "phi")) ||
+      (r = dalloc(&c->accel, sizeof(double) * 3 * c->np, "accel")) ||
+      (r = dalloc(&c->work, sizeof(double2) * wn, "transform work")) ||
+      (r = dalloc(&c->part, sizeof(double) * 2 * c->np, "partials")) ||
+      (r = dalloc(&c->red, sizeof(double) * 8, "reduction"))) {
+    release(c);
+    return r;
+  }
+  for (int ax = 0; ax < 3; ax++) {
+    if ((r = dalloc(&c->tw[ax], sizeof(double2) * c->wg.m[ax], "twiddles"))) {
+      release(c);
+      return r;
+    }
+  }
+  if (cfg->bc == VP_BC_ISOLATED && (r = dalloc(&c->kspec, sizeof(double2) * wn, "green spectrum"))) {
+    release(c);
+    return r;
+  }
+  hipError_t he = hipHostMalloc((void**)&c->host, sizeof(double) * 8, hipHostMallocDefault);
+  if (he != hipSuccess) {
+    c->host = nullptr;
+    release(c);
+    return fail(VP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(he));
+  }
+  for (int ax = 0; ax < 3; ax++) {
+    if ((r = check_launch(c, vp::launch_twiddles(c->tw[ax], c->wg.m[ax], c->stream), "twiddles"))) {
+      release(c);
+      return r;
+    }
+  }
+  if (cfg->bc == VP_BC_ISOLATED) {
+    const double self = -cfg->G * 8.0 * corner_integral(0.5 * c->dx[0], 0.5 * c->dx[1], 0.5 * c->dx[2]);
+    r = check_launch(c, vp::launch_green_isolated(c->kspec, c->wg, cfg->G, c->dx[0], c->dx[1], c->dx[2], self,
+                                                  c->stream), "green");
+    for (int ax = 0; ax < 3 && r == VP_OK; ax++)
+      r = check_launch(c, vp::launch_dft_axis(c->kspec, c->wg, ax, -1, c->tw[ax], c->stream), "green dft");
+    if (r != VP_OK) {
+      release(c);
+      return r;
+    }
+  }
+  r = compute_accel(c);
+  if (r != VP_OK) {
+    hipStreamSynchronize(c->stream);
+    release(c);
+    return r;
+  }
+  *out = c;
+  return VP_OK;
+}
+
+int vp_sweep(vp_ctx* c, int32_t axis, double tau)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (axis < 0 || axis > 5) return fail(VP_EINVAL, "axis must be 0..5");
+  if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
+  return sweep(c, axis, tau);
+}
+
+int vp_step(vp_ctx* c, double dt)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!(std::isfinite(dt) && dt > 0)) return fail(VP_EINVAL, "dt must be finite and > 0");
+  const double h = 0.5 * dt;
+  if ((r = sweep(c, 3, h)) || (r = sweep(c, 4, h)) || (r = sweep(c, 5, h))) return r;
+  if ((r = sweep(c, 2, dt)) || (r = sweep(c, 1, dt)) || (r = sweep(c, 0, dt))) return r;
+  if ((r = compute_accel(c))) return r;
+  if ((r = sweep(c, 3, h)) || (r = sweep(c, 4, h)) || (r = sweep(c, 5, h))) return r;
+  return VP_OK;
+}
+
+int vp_run(vp_ctx* c, int32_t nsteps, double dt)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (nsteps < 0) return fail(VP_EINVAL, "nsteps must be >= 0");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(VP_EINVAL, "dt must be finite and > 0");
+  for (int i = 0; i < nsteps; i++)
+    if ((r = vp_step(c, dt))) return r;
+  return VP_OK;
+}
+
+int vp_accel(vp_ctx* c)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  return compute_accel(c);
+}
+
+int vp_get_accel(vp_ctx* c, double* a_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!a_dev) return fail(VP_EINVAL, "null pointer");
+  HIP_TRY(hipMemcpyAsync(a_dev, c->accel, sizeof(double) * 3 * c->np, hipMemcpyDeviceToDevice, c->stream));
+  return VP_OK;
+}
+
+int vp_set_accel(vp_ctx* c, const double* a_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!a_dev) return fail(VP_EINVAL, "null pointer");
+  HIP_TRY(hipMemcpyAsync(c->accel, a_dev, sizeof(double) * 3 * c->np, hipMemcpyDeviceToDevice, c->stream));
+  return VP_OK;
+}
+
+int vp_density(vp_ctx* c, double* rho_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!rho_dev) return fail(VP_EINVAL, "null pointer");
+  LAUNCH(c, vp::launch_density(c->f, c->cfg.dtype, rho_dev, c->np, c->nv3, c->dv[0] * c->dv[1] * c->dv[2],
+                               c->stream));
+  return VP_OK;
+}
+
+int vp_potential(vp_ctx* c, double* phi_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!phi_dev) return fail(VP_EINVAL, "null pointer");
+  return potential_into(c, phi_dev);
+}
+
+int vp_energy(vp_ctx* c, double out_host[4])
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!out_host) return fail(VP_EINVAL, "null pointer");
+  if ((r = potential_into(c, c->phi))) return r;
+  vp::VelGrid vg{};
+  for (int l = 0; l < 3; l++) {
+    vg.nv[l] = c->cfg.nv[l];
+    vg.vmin[l] = c->cfg.vmin[l];
+    vg.dv[l] = c->dv[l];
+  }
+  LAUNCH(c, vp::launch_energy_partials(c->f, c->cfg.dtype, c->part, c->np, vg, c->stream));
+  LAUNCH(c, vp::launch_energy_final(c->red, c->part, c->rho, c->phi, c->ng, c->dx[0] * c->dx[1] * c->dx[2],
+                                    c->dv[0] * c->dv[1] * c->dv[2], c->stream));
+  HIP_TRY(hipMemcpyAsync(c->host, c->red, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 4; i++) out_host[i] = c->host[i];
+  for (int i = 0; i < 4; i++)
+    if (!std::isfinite(out_host[i])) return fail(VP_ENONFINITE, "diagnostic %d is not finite", i);
+  return VP_OK;
+}
+
+int vp_dt(vp_ctx* c, double cfl, double* dt_host)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!dt_host) return fail(VP_EINVAL, "null pointer");
+  if (!(std::isfinite(cfl) && cfl > 0)) return fail(VP_EINVAL, "cfl must be finite and > 0");
+  LAUNCH(c, vp::launch_accel_max(c->red, c->accel, c->np, 1.0 / c->dv[0], 1.0 / c->dv[1], 1.0 / c->dv[2],
+                                 c->stream));
+  HIP_TRY(hipMemcpyAsync(c->host, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double dtp = INFINITY;
+  for (int l = 0; l < 3; l++) {
+    const double vm = std::fmax(std::fabs(c->cfg.vmin[l]), std::fabs(c->cfg.vmax[l]));
+    if (vm > 0) dtp = std::fmin(dtp, c->dx[l] / vm);
+  }
+  const double amax = c->host[0];
+  const double dtv = amax > 0 ? 1.0 / amax : INFINITY;
+  *dt_host = cfl * std::fmin(dtp, dtv);
+  return VP_OK;
+}
+
+int vp_free(vp_ctx* c)
+{
+  g_err.clear();
+  if (!c) return VP_OK;
+  hipStreamSynchronize(c->stream);
+  release(c);
+  return VP_OK;
+}
+
+const char* vp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

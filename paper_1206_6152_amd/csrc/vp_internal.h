@@ -1,0 +1,94 @@
+// vp_internal.h -- declarations shared by the library's HIP translation units
+// (kernels and the host C-ABI). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vp {
+
+// Geometry and Courant-number rule of one directional sweep. The array is
+// viewed as [outer][n][inner]: a line is (o, c) and its cells sit at
+// (o*n + r)*inner + c for r = 0..n-1.
+struct SweepArgs {
+  void* f;
+  long long outer;     // number of slabs
+  long long inner;     // stride between consecutive cells of a line
+  long long nlines;    // outer * inner
+  int n;               // line length
+  int velocity;        // 1: nu = accel[o / sp_div] * scale; 0: nu = v_j * scale
+  int periodic;        // 1: periodic ghosts; 0: outflow ghosts
+  int pad0;
+  double scale;        // tau / dv (velocity) or tau / dx (position)
+  const double* accel; // acceleration component (velocity sweeps)
+  long long sp_div;    // spatial cell of slab o is o / sp_div (velocity sweeps)
+  long long j_div;     // velocity index j = (c / j_div) % j_mod (position sweeps)
+  long long j_mod;
+  double vmin, dv;     // cell-centre velocity v_j = vmin + (j + 1/2) dv
+};
+
+// Launch one sweep on the stream; dtype 0 = float, 1 = double.
+hipError_t launch_sweep(const SweepArgs& a, int dtype, hipStream_t s);
+
+// True when n is a line length the sweep kernels are instantiated for.
+bool sweep_length_supported(int n);
+
+// ---- gravity and reductions (FP64) ----------------------------------------
+
+// rho[s] = dv3 * sum_j f[s*nv3 + j]
+hipError_t launch_density(const void* f, int dtype, double* rho, long long np, long long nv3,
+                          double dv3, hipStream_t s);
+
+struct Grid3 {
+  int m[3];
+};
+
+// Twiddle table w[k] = exp(-2 pi i k / M), k = 0..M-1, as (cos, sin) pairs.
+hipError_t launch_twiddles(double2* w, int M, hipStream_t s);
+
+// In-place DFT along one axis of a complex field of shape g (C order);
+// sign -1 forward, +1 inverse (no scaling). tw is the table for g.m[axis].
+hipError_t launch_dft_axis(double2* data, Grid3 g, int axis, int sign, const double2* tw,
+                           hipStream_t s);
+
+// data = rho (imag 0) on an n-grid (periodic) or zero-padded into the 2n-grid.
+hipError_t launch_load_rho(double2* data, Grid3 g, const double* rho, Grid3 n, hipStream_t s);
+
+// data *= G_hat(k) of the periodic discrete Green's function; zero mode -> 0.
+hipError_t launch_green_periodic(double2* data, Grid3 g, double G, double d0, double d1,
+                                 double d2, hipStream_t s);
+
+// data *= spec (complex, same grid)
+hipError_t launch_mul_spectrum(double2* data, const double2* spec, long long count, hipStream_t s);
+
+// Real-space isolated Green's function on the doubled grid (offsets mirrored).
+hipError_t launch_green_isolated(double2* data, Grid3 g, double G, double d0, double d1,
+                                 double d2, double self_value, hipStream_t s);
+
+// phi_ext[t] (t in -1..n per axis) = scale * Re data[t mod g]
+hipError_t launch_extract_phi(double* phi_ext, Grid3 n, const double2* data, Grid3 g,
+                              double scale, hipStream_t s);
+
+// a_l = -(phi(i+e_l) - phi(i-e_l)) / (2 d_l) from the ghost-padded potential.
+hipError_t launch_gradient(double* accel, const double* phi_ext, Grid3 n, double d0, double d1,
+                           double d2, hipStream_t s);
+
+// Partial sums per spatial cell: part[2*s] = sum f, part[2*s+1] = sum f |v|^2.
+struct VelGrid {
+  int nv[3];
+  double vmin[3];
+  double dv[3];
+};
+hipError_t launch_energy_partials(const void* f, int dtype, double* part, long long np,
+                                  VelGrid vg, hipStream_t s);
+
+// out[0..3] = K, U, M, E from the partials, rho and phi_ext (deterministic).
+hipError_t launch_energy_final(double* out, const double* part, const double* rho,
+                               const double* phi_ext, Grid3 n, double dx3, double dv3,
+                               hipStream_t s);
+
+// out[0] = max over cells and axes of |a_l| * inv_dv[l].
+hipError_t launch_accel_max(double* out, const double* accel, long long np, double i0, double i1,
+                            double i2, hipStream_t s);
+
+}  // namespace vp

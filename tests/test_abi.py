@@ -1,0 +1,106 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, agrees with the binding on the config layout, and validates
+configurations on the host before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1206_6152_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _built():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1206_6152_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "vp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _built()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_config_layout_matches():
+    L = _built()
+    assert L.vp_config_size() == ctypes.sizeof(_lib.vp_config)
+
+
+def _good():
+    return _lib.make_config((8, 8, 8), (16, 16, 16), (1, 1, 1), (-1, -1, -1), (1, 1, 1))
+
+
+def test_validate_accepts_good_config():
+    _built()
+    assert _lib.vp_config_validate(_good()) == _lib.VP_OK
+    c = _good()
+    c.bc = _lib.VP_BC_ISOLATED
+    c.dtype = _lib.VP_F64
+    assert _lib.vp_config_validate(c) == _lib.VP_OK
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n", (0, 8, 8), _lib.VP_EINVAL),
+    ("nv", (16, -1, 16), _lib.VP_EINVAL),
+    ("n", (10, 8, 8), _lib.VP_EUNSUPPORTED),
+    ("nv", (16, 16, 20), _lib.VP_EUNSUPPORTED),
+    ("L", (1, 0, 1), _lib.VP_EINVAL),
+    ("L", (1, float("nan"), 1), _lib.VP_EINVAL),
+    ("vmax", (1, -1, 1), _lib.VP_EINVAL),
+    ("G", -1.0, _lib.VP_EINVAL),
+    ("bc", 7, _lib.VP_EINVAL),
+    ("dtype", 2, _lib.VP_EINVAL),
+    ("flags", 1, _lib.VP_EINVAL),
+])
+def test_validate_rejects(field, value, code):
+    _built()
+    c = _good()
+    if isinstance(value, tuple):
+        arr = getattr(c, field)
+        for i, v in enumerate(value):
+            arr[i] = v
+    else:
+        setattr(c, field, value)
+    assert _lib.vp_config_validate(c) == code
+    assert _lib.vp_last_error() != ""
+
+
+def test_isolated_needs_equal_spacing():
+    _built()
+    c = _good()
+    c.bc = _lib.VP_BC_ISOLATED
+    c.L[1] = 2.0
+    assert _lib.vp_config_validate(c) == _lib.VP_EUNSUPPORTED
+
+
+def test_init_rejects_null_pointers_before_device_work():
+    L = _built()
+    c = _good()
+    ctx = ctypes.c_void_p()
+    assert L.vp_init(ctypes.byref(c), None, None, ctypes.byref(ctx)) == _lib.VP_EINVAL
+    assert ctx.value is None
+    assert L.vp_init(ctypes.byref(c), ctypes.c_void_p(1), None, None) == _lib.VP_EINVAL
+    assert L.vp_init(None, ctypes.c_void_p(1), None, ctypes.byref(ctx)) == _lib.VP_EINVAL
+
+
+def test_calls_reject_null_context():
+    L = _built()
+    assert L.vp_step(None, 0.1) == _lib.VP_EINVAL
+    assert L.vp_sweep(None, 0, 0.1) == _lib.VP_EINVAL
+    assert L.vp_free(None) == _lib.VP_OK
+    with pytest.raises(_lib.VPError):
+        _lib.vp_step(None, 0.1)
