@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the six-dimensional PFC Vlasov-Poisson step on one MI355X.
+
+Workload (default): the Jeans-instability cube, periodic unit box, k/k_J = 0.5,
+A = 0.01 cosine along x on a Maxwellian, 32^3 spatial x 32^3 velocity cells
+(1.07e9 phase-space cells), fixed dt (CFL 0.5). One step is one application of
+the split operator product (nine directional sweeps, one density moment and
+one Poisson solve). Inputs are synthetic and built on the device before the
+timed region; f stays resident in HBM.
+
+Prints ONE JSON line: value = phase-space cell updates per second with f stored
+and swept in FP32 (density/Poisson/acceleration in FP64), plus the FP64-stored
+rate, the roofline of the dominant sweep kernel (HIP events around every
+launch on the library's stream), per-phase times in the layout of the paper's
+Table 1, the measured device-copy bandwidth, and the CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E, AMD public specification
+METRIC = "phase-space cell updates/s (FP32 vs FP64 GPU) + % HBM roofline"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_f(w, torch_dtype, device):
+    """f = (spatial factor) x (velocity factor), formed on the device in FP64 and
+    rounded once to the storage type, chunk by chunk."""
+    import torch
+    from paper_1206_6152_amd import inputs
+    dens, m = inputs.separable_factors(w)
+    d = torch.from_numpy(dens.reshape(-1)).to(device)
+    mv = torch.from_numpy(m.reshape(-1)).to(device)
+    np_, nv3 = d.numel(), mv.numel()
+    f = torch.empty(w.shape, dtype=torch_dtype, device=device)
+    fv = f.view(np_, nv3)
+    chunk = max(1, (1 << 27) // nv3)
+    for i in range(0, np_, chunk):
+        fv[i:i + chunk] = (d[i:i + chunk, None] * mv[None, :]).to(torch_dtype)
+    torch.cuda.synchronize()
+    return f
+
+
+def copy_bandwidth(f):
+    """GB/s of a plain device copy of a tensor of f's size (read + write)."""
+    import torch
+    g = torch.empty_like(f)
+    g.copy_(f)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        g.copy_(f)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * f.numel() * f.element_size()
+    del g
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def gpu_run(w, vp_dtype, steps, warmup):
+    import torch
+    from paper_1206_6152_amd import VP_F32, Simulator, config_of
+    tdt = torch.float32 if vp_dtype == VP_F32 else torch.float64
+    dev = torch.device("cuda:0")
+    f = build_f(w, tdt, dev)
+    copy_gbps = copy_bandwidth(f)
+    sim = Simulator(config_of(w, vp_dtype), f)
+    e_start = sim.energy()
+    sim.run(warmup, w.dt)
+    torch.cuda.synchronize()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps, w.dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = sim.profile_read()
+    sim.profile(False)
+    e_end = sim.energy()
+    sim.close()
+    s = f.element_size()
+    cells = w.cells
+    del f
+    torch.cuda.empty_cache()
+    per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in phases.items()}
+    sweep_tot = {k: phases[k][0] for k in ("x", "y", "z", "vx", "vy", "vz")}
+    dom = max(sweep_tot, key=sweep_tot.get)
+    dom_ms = per_launch[dom]
+    sweep_bytes = 2.0 * s * cells          # read + write f once per sweep
+    achieved = sweep_bytes / (dom_ms * 1e-3) / 1e9
+    step_ms = wall * 1e3 / steps
+    step_bytes = 19.0 * s * cells          # 9 sweeps x 2 + one density read
+    return dict(
+        value=cells * steps / wall,
+        ms_per_step=step_ms,
+        bytes_per_elem=s,
+        dominant=dom,
+        roofline=dict(bound="hbm", kernel="pfc sweep along %s" % dom, achieved=achieved,
+                      peak=PEAK_HBM_GBPS, unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
+                      traffic=None, algorithmic_bytes_per_launch=sweep_bytes,
+                      avg_launch_ms=dom_ms),
+        step_roofline=dict(model_bytes_per_step=step_bytes,
+                           achieved_GBps=step_bytes / (step_ms * 1e-3) / 1e9,
+                           frac=step_bytes / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS),
+        phases_ms_per_launch=per_launch,
+        phases_launches={k: n for k, (ms, n) in phases.items()},
+        copy_GBps=copy_gbps,
+        mass_drift=(e_end[2] - e_start[2]) / e_start[2],
+    )
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle, as it is, on a bounded sample of the workload: the same
+    velocity grid and physics on an 8^3 spatial sub-grid, stepped for about
+    `seconds` of wall time on the host's cores."""
+    import numpy as np
+
+    import oracle
+    from paper_1206_6152_amd import inputs
+    sub = inputs.Workload(name=w.name, n=(8, 8, 8), nv=w.nv, L=(0.25, 0.25, 0.25), vmin=w.vmin,
+                          vmax=w.vmax, G=w.G, bc=w.bc, dt=w.dt, steps=1, params=w.params)
+    f0 = inputs.initial_f(sub)
+    g = oracle.Grid(n=sub.n, nv=sub.nv, L=sub.L, vmin=sub.vmin, vmax=sub.vmax, G=sub.G, bc=sub.bc)
+    run = oracle.Run(g, f0)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        run.step(sub.dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    cells = sub.cells
+    return dict(value=cells * steps / el, unit="cell-updates/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample="FP64 oracle, %d steps of an 8^3-spatial x %s-velocity sub-grid of the same "
+                       "workload (%.3g cells, same Courant numbers), %.1f s wall; host %s, %d logical CPUs"
+                       % (steps, "x".join(map(str, sub.nv)), cells, el, platform.processor() or
+                          platform.machine(), os.cpu_count() or 0))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="jeans_32x32")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-stored run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the multi-GPU (x-slab) decomposition is a "
+              "design only in this build; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1206_6152_amd import VP_F32, VP_F64, inputs
+    w = inputs.WORKLOADS[args.workload]()
+    log("workload", w.name, "cells", w.cells, "dt", w.dt)
+
+    r32 = gpu_run(w, VP_F32, args.steps, args.warmup)
+    log("fp32", json.dumps(r32))
+    r64 = None
+    if not args.no_fp64:
+        r64 = gpu_run(w, VP_F64, args.steps, args.warmup)
+        log("fp64", json.dumps(r64))
+    cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
+    if cpu:
+        log("cpu", json.dumps(cpu))
+
+    out = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "description": "periodic unit cube, G=rho0=1, k/k_J=0.5, A=0.01 cosine along x on a "
+                           "Maxwellian, v in [-5s,5s]^3, %s spatial x %s velocity cells, fixed dt=%.6g; "
+                           "f stored/swept in FP32, density/Poisson/acceleration FP64"
+                           % ("x".join(map(str, w.n)), "x".join(map(str, w.nv)), w.dt),
+            "cells": w.cells,
+            "sweeps_per_step": 9,
+            "parallelism": "single GPU",
+        },
+        "roofline": r32["roofline"],
+        "step_roofline": r32["step_roofline"],
+        "phases_ms_per_launch": r32["phases_ms_per_launch"],
+        "copy_GBps": r32["copy_GBps"],
+        "cpu_baseline": cpu,
+    }
+    if r64:
+        out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"],
+                       "step_roofline": r64["step_roofline"],
+                       "phases_ms_per_launch": r64["phases_ms_per_launch"]}
+        out["fp32_over_fp64"] = r32["value"] / r64["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

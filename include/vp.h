@@ -82,7 +82,7 @@ int vp_config_size(void);
 int vp_config_validate(const vp_config* cfg);
 
 /* Create a context on the current HIP device for the f array at f_dev (device
- * pointer, layout and type above, caller-owned). The library BORROWS f: it
+ * pointer, 16-byte aligned, layout and type above, caller-owned). The library BORROWS f: it
  * updates it in place and the caller keeps it alive, and does not modify it
  * behind the library's back, until vp_free. hip_stream is a hipStream_t (NULL
  * for the null stream). Allocates the FP64 work fields and computes the
@@ -135,6 +135,19 @@ int vp_energy(vp_ctx* ctx, double out_host[4]);
  * with V^max = max(|vmin|, |vmax|) per axis; an axis with no velocity extent
  * or no acceleration imposes no limit. Synchronises the stream. */
 int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
+
+/* Per-phase timing, the breakdown of the paper's Table 1 (Sec. 4): when
+ * enabled, every sweep and every gravity solve issued by vp_step, vp_run,
+ * vp_sweep and vp_accel is bracketed by HIP events on the context's stream.
+ * vp_profile_enable(ctx, 1) clears the totals and starts recording;
+ * vp_profile_enable(ctx, 0) stops. vp_profile_read synchronises the stream and
+ * returns, per phase, the summed event time in milliseconds and the number of
+ * launches: phases 0..5 are the sweeps along x, y, z, vx, vy, vz, phase 6 the
+ * gravity solve (density, Poisson, acceleration). Arrays have VP_NPHASE
+ * entries and are caller-owned host memory. */
+#define VP_NPHASE 7
+int vp_profile_enable(vp_ctx* ctx, int32_t on);
+int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 
 /* Release everything the context owns (never f). NULL is accepted. */
 int vp_free(vp_ctx* ctx);

@@ -11,13 +11,14 @@ from __future__ import annotations
 from . import _lib
 from ._lib import (VP_BC_ISOLATED, VP_BC_PERIODIC, VP_F32, VP_F64, VPError, make_config,
                    vp_accel, vp_config_validate, vp_density, vp_dt, vp_energy, vp_free,
-                   vp_get_accel, vp_init, vp_last_error, vp_potential, vp_run, vp_set_accel,
-                   vp_step, vp_sweep)
+                   vp_get_accel, vp_init, vp_last_error, vp_potential, vp_profile_enable,
+                   vp_profile_read, vp_run, vp_set_accel, vp_step, vp_sweep)
 
 __all__ = ["Simulator", "VPError", "make_config", "config_of", "VP_F32", "VP_F64",
            "VP_BC_PERIODIC", "VP_BC_ISOLATED", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential",
-           "vp_energy", "vp_dt", "vp_free", "vp_last_error", "vp_config_validate"]
+           "vp_energy", "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_free",
+           "vp_last_error", "vp_config_validate"]
 
 
 def config_of(w, dtype: int = VP_F32):
@@ -91,6 +92,12 @@ class Simulator:
 
     def dt(self, cfl: float) -> float:
         return vp_dt(self.ctx, cfl)
+
+    def profile(self, on: bool = True):
+        vp_profile_enable(self.ctx, on)
+
+    def profile_read(self):
+        return vp_profile_read(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -31,7 +31,9 @@ ERROR_NAMES = {VP_EINVAL: "VP_EINVAL", VP_ENOMEM: "VP_ENOMEM", VP_EHIP: "VP_EHIP
 # every symbol include/vp.h declares
 EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential", "vp_energy",
-           "vp_dt", "vp_free", "vp_last_error"]
+           "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_free", "vp_last_error"]
+VP_NPHASE = 7
+PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity"]
 
 
 class VPError(RuntimeError):
@@ -87,6 +89,8 @@ def lib():
             "vp_potential": [P, P],
             "vp_energy": [P, D],
             "vp_dt": [P, f64, D],
+            "vp_profile_enable": [P, i32],
+            "vp_profile_read": [P, D, ctypes.POINTER(ctypes.c_int64)],
             "vp_free": [P],
             "vp_last_error": [],
         }
@@ -176,6 +180,18 @@ def vp_dt(ctx: int, cfl: float) -> float:
     out = ctypes.c_double()
     check(lib().vp_dt(ctx, float(cfl), ctypes.byref(out)))
     return out.value
+
+
+def vp_profile_enable(ctx: int, on: bool) -> None:
+    check(lib().vp_profile_enable(ctx, 1 if on else 0))
+
+
+def vp_profile_read(ctx: int):
+    """{phase: (total ms, launches)} since profiling was enabled (synchronises)."""
+    ms = (ctypes.c_double * VP_NPHASE)()
+    n = (ctypes.c_int64 * VP_NPHASE)()
+    check(lib().vp_profile_read(ctx, ms, n))
+    return {PHASES[i]: (ms[i], n[i]) for i in range(VP_NPHASE)}
 
 
 def vp_free(ctx: int) -> None:

@@ -41,15 +41,50 @@ __device__ __forceinline__ double block_max(double x, double* sh)
   return r;
 }
 
-// rho = dv3 * sum over the contiguous velocity block of one spatial cell
+// rho = dv3 * sum over the contiguous velocity block of one spatial cell.
+// 16-byte loads, four independent accumulators per lane so that several loads
+// are in flight, then a fixed-order tree over the workgroup (deterministic).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+};
+
+template <typename T>
+__device__ __forceinline__ double vsum(const float4& v) { return ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w); }
+template <typename T>
+__device__ __forceinline__ double vsum(const double2& v) { return v.x + v.y; }
+
 template <typename T>
 __global__ __launch_bounds__(RED) void density_kernel(const T* f, double* rho, long long nv3, double dv3)
 {
   __shared__ double sh[RED];
+  using VT = typename Vec16<T>::type;
+  constexpr int V = 16 / sizeof(T);
   const T* p = f + (long long)blockIdx.x * nv3;
-  double acc = 0.0;
-  for (long long j = threadIdx.x; j < nv3; j += RED) acc += (double)p[j];
-  const double s = block_sum(acc, sh);
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  long long done = 0;
+  if ((nv3 % V) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0) {
+    const VT* pv = reinterpret_cast<const VT*>(p);
+    const long long nvec = nv3 / V;
+    long long i = threadIdx.x;
+    for (; i + 3 * RED < nvec; i += 4 * RED) {
+      const VT a = pv[i], b = pv[i + RED], c = pv[i + 2 * RED], d = pv[i + 3 * RED];
+      acc0 += vsum<T>(a);
+      acc1 += vsum<T>(b);
+      acc2 += vsum<T>(c);
+      acc3 += vsum<T>(d);
+    }
+    for (; i < nvec; i += RED) acc0 += vsum<T>(pv[i]);
+    done = nv3;
+  }
+  for (long long j = done + threadIdx.x; j < nv3; j += RED) acc0 += (double)p[j];
+  const double s = block_sum((acc0 + acc1) + (acc2 + acc3), sh);
   if (threadIdx.x == 0) rho[blockIdx.x] = s * dv3;
 }
 

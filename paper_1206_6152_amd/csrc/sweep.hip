@@ -149,31 +149,104 @@ struct ContigShape {
   static constexpr int lines = (256 * bytes <= 40960) ? 256 : (128 * bytes <= 40960) ? 128 : 64;
 };
 
-// Contiguous lines (inner == 1): coalesced copy of LINES lines into LDS, one
-// lane per line in registers, coalesced copy back.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+
+template <typename VT, typename T>
+__device__ __forceinline__ T lane_of(const VT& v, int q)
+{
+  return reinterpret_cast<const T*>(&v)[q];
+}
+
+// Contiguous lines (inner == 1): a workgroup takes LINES consecutive lines
+// (one contiguous block of LINES*N elements), copies it into LDS with
+// coalesced 16-byte loads (all issued before the first LDS write), gives each
+// lane one line in registers, and copies the result back the same way. The LDS
+// rows are padded to N+1 elements so the per-line accesses hit distinct banks.
 template <typename T, int N>
 __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(SweepArgs a)
 {
   constexpr int LINES = ContigShape<T, N>::lines;
   constexpr int P = N + 1;
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::n;
+  constexpr bool VEC = (N % V) == 0;
+  constexpr int PER = VEC ? N / V : N;   // loads per lane for a full tile
   __shared__ T tile[LINES * P];
+  const int tid = threadIdx.x;
   const long long line0 = (long long)blockIdx.x * LINES;
   const long long left = a.nlines - line0;
   const int nl = left < LINES ? (int)left : LINES;
-  const int count = nl * N;
   T* g = static_cast<T*>(a.f) + line0 * N;
-  for (int e = threadIdx.x; e < count; e += LINES) tile[(e / N) * P + (e % N)] = g[e];
-  __syncthreads();
-  if ((int)threadIdx.x < nl) {
-    T v[N];
+  if (nl == LINES) {
+    if constexpr (VEC) {
+      const VT* gv = reinterpret_cast<const VT*>(g);
+      VT x[PER];
 #pragma unroll
-    for (int r = 0; r < N; r++) v[r] = tile[threadIdx.x * P + r];
-    pfc_line<T, N>(v, line_nu(a, line0 + threadIdx.x, 0), a.periodic != 0);
+      for (int k = 0; k < PER; k++) x[k] = gv[tid + k * LINES];
 #pragma unroll
-    for (int r = 0; r < N; r++) tile[threadIdx.x * P + r] = v[r];
+      for (int k = 0; k < PER; k++) {
+        const int e = (tid + k * LINES) * V;
+#pragma unroll
+        for (int q = 0; q < V; q++) tile[((e + q) / N) * P + ((e + q) % N)] = lane_of<VT, T>(x[k], q);
+      }
+    } else {
+      T x[PER];
+#pragma unroll
+      for (int k = 0; k < PER; k++) x[k] = g[tid + k * LINES];
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int e = tid + k * LINES;
+        tile[(e / N) * P + (e % N)] = x[k];
+      }
+    }
+  } else {
+    const int count = nl * N;
+    for (int e = tid; e < count; e += LINES) tile[(e / N) * P + (e % N)] = g[e];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < count; e += LINES) g[e] = tile[(e / N) * P + (e % N)];
+  if (tid < nl) {
+    T v[N];
+#pragma unroll
+    for (int r = 0; r < N; r++) v[r] = tile[tid * P + r];
+    pfc_line<T, N>(v, line_nu(a, line0 + tid, 0), a.periodic != 0);
+#pragma unroll
+    for (int r = 0; r < N; r++) tile[tid * P + r] = v[r];
+  }
+  __syncthreads();
+  if (nl == LINES) {
+    if constexpr (VEC) {
+      VT* gv = reinterpret_cast<VT*>(g);
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int e = (tid + k * LINES) * V;
+        VT x;
+        T* xs = reinterpret_cast<T*>(&x);
+#pragma unroll
+        for (int q = 0; q < V; q++) xs[q] = tile[((e + q) / N) * P + ((e + q) % N)];
+        gv[tid + k * LINES] = x;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int e = tid + k * LINES;
+        g[e] = tile[(e / N) * P + (e % N)];
+      }
+    }
+  } else {
+    const int count = nl * N;
+    for (int e = tid; e < count; e += LINES) g[e] = tile[(e / N) * P + (e % N)];
+  }
 }
 
 template <typename T, int N>

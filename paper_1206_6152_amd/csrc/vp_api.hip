@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "vp.h"
 #include "vp_internal.h"
@@ -62,6 +63,12 @@ struct vp_ctx {
   double* part = nullptr;     // 2 * np
   double* red = nullptr;      // 8 doubles on the device
   double* host = nullptr;     // 8 pinned doubles
+  // phase timing (vp_profile_*): pending event pairs per phase
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double phase_ms[VP_NPHASE] = {0, 0, 0, 0, 0, 0, 0};
+  long long phase_n[VP_NPHASE] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -112,6 +119,11 @@ void release(vp_ctx* c)
   hipFree(c->part);
   hipFree(c->red);
   if (c->host) hipHostFree(c->host);
+  for (auto& p : c->ev_pending) {
+    hipEventDestroy(p.second.first);
+    hipEventDestroy(p.second.second);
+  }
+  for (auto e : c->ev_free) hipEventDestroy(e);
   delete c;
 }
 
@@ -128,6 +140,54 @@ int dalloc(P** p, size_t bytes, const char* what)
 }
 
 long long prod3(const int m[3]) { return (long long)m[0] * m[1] * m[2]; }
+
+hipEvent_t take_event(vp_ctx* c)
+{
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one phase with events when profiling is on.
+struct PhaseScope {
+  vp_ctx* c;
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseScope(vp_ctx* c_, int p) : c(c_), phase(p)
+  {
+    if (!c->profiling) return;
+    a = take_event(c);
+    b = take_event(c);
+    if (a) hipEventRecord(a, c->stream);
+  }
+  ~PhaseScope()
+  {
+    if (!c->profiling || !a || !b) return;
+    hipEventRecord(b, c->stream);
+    c->ev_pending.push_back({phase, {a, b}});
+  }
+};
+
+// Fold finished event pairs into the totals (synchronises the stream).
+int drain_events(vp_ctx* c)
+{
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& p : c->ev_pending) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    c->phase_ms[p.first] += ms;
+    c->phase_n[p.first] += 1;
+    c->ev_free.push_back(p.second.first);
+    c->ev_free.push_back(p.second.second);
+  }
+  c->ev_pending.clear();
+  return VP_OK;
+}
 
 // density -> rho, Poisson -> phi (with ghosts)
 int potential_into(vp_ctx* c, double* phi_out)
@@ -148,6 +208,7 @@ int potential_into(vp_ctx* c, double* phi_out)
 
 int compute_accel(vp_ctx* c)
 {
+  PhaseScope scope(c, 6);
   int r = potential_into(c, c->phi);
   if (r != VP_OK) return r;
   LAUNCH(c, vp::launch_gradient(c->accel, c->phi, c->ng, c->dx[0], c->dx[1], c->dx[2], c->stream));
@@ -187,6 +248,7 @@ int sweep(vp_ctx* c, int axis, double tau)
     a.dv = c->dv[axis];
     a.sp_div = 1;
   }
+  PhaseScope scope(c, axis);
   LAUNCH(c, vp::launch_sweep(a, k.dtype, c->stream));
   return VP_OK;
 }
@@ -241,6 +303,7 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
   int r = vp_config_validate(cfg);
   if (r != VP_OK) return r;
   if (!f_dev) return fail(VP_EINVAL, "null f pointer");
+  if (reinterpret_cast<uintptr_t>(f_dev) % 16 != 0) return fail(VP_EINVAL, "f must be 16-byte aligned");
   vp_ctx* c = new (std::nothrow) vp_ctx;
   if (!c) return fail(VP_ENOMEM, "host allocation failed");
   c->cfg = *cfg;
@@ -436,6 +499,36 @@ int vp_dt(vp_ctx* c, double cfl, double* dt_host)
   const double amax = c->host[0];
   const double dtv = amax > 0 ? 1.0 / amax : INFINITY;
   *dt_host = cfl * std::fmin(dtp, dtv);
+  return VP_OK;
+}
+
+int vp_profile_enable(vp_ctx* c, int32_t on)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if ((r = drain_events(c))) return r;
+  c->profiling = on != 0;
+  if (c->profiling) {
+    for (int i = 0; i < VP_NPHASE; i++) {
+      c->phase_ms[i] = 0;
+      c->phase_n[i] = 0;
+    }
+  }
+  return VP_OK;
+}
+
+int vp_profile_read(vp_ctx* c, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE])
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!ms_out || !count_out) return fail(VP_EINVAL, "null pointer");
+  if ((r = drain_events(c))) return r;
+  for (int i = 0; i < VP_NPHASE; i++) {
+    ms_out[i] = c->phase_ms[i];
+    count_out[i] = c->phase_n[i];
+  }
   return VP_OK;
 }
 

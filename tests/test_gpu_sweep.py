@@ -120,3 +120,20 @@ def test_ragged_line_counts(dtype):
         out = gpu_sweep(w, f0, dtype, axis, tau, accel if axis >= 3 else None)
         tol = 1e-14 if dtype == VP_F64 else 1e-6
         assert rel_l1(out, ref) <= tol, axis
+
+
+@pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
+@pytest.mark.parametrize("nvl", [8, 24, 32, 48, 64])
+def test_velocity_line_lengths_of_the_workloads(nvl, dtype):
+    # the velocity line lengths of the benchmark workloads, on every velocity
+    # axis, with enough lines for several full workgroups and a ragged tail
+    w = small_workload(VP_BC_PERIODIC, n=(2, 3, 2), nv=(nvl, 3, nvl))
+    f0 = structured_f(w.shape, seed=nvl).astype(NP[dtype]).astype(np.float64)
+    g = oracle_grid(w)
+    for axis in (3, 4, 5):
+        tau = 0.3
+        accel = random_accel(w, 0.95, tau, seed=axis + nvl)
+        ref = oracle.sweep(g, f0, axis, tau, accel)
+        out = gpu_sweep(w, f0, dtype, axis, tau, accel)
+        tol = 1e-14 if dtype == VP_F64 else 1e-6
+        assert rel_l1(out, ref) <= tol, axis
