@@ -108,6 +108,15 @@ int vp_run(vp_ctx* ctx, int32_t nsteps, double dt);
  * any Courant number). */
 int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
 
+/* The two halves of Eq. (17). vp_kick: T_vz T_vy T_vx(tau) with the stored
+ * acceleration (T_vx first). vp_drift: T_x T_y T_z(tau) (T_z first). Each is
+ * exactly the corresponding vp_sweep calls in that order (same arithmetic, same
+ * result bit for bit); vp_kick runs the three velocity sweeps of a spatial
+ * cell in one pass over f when that cell's velocity block fits on chip
+ * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3). */
+int vp_kick(vp_ctx* ctx, double tau);
+int vp_drift(vp_ctx* ctx, double tau);
+
 /* Recompute the stored acceleration from the current f (Eqs. (18)-(22)). */
 int vp_accel(vp_ctx* ctx);
 
@@ -143,9 +152,9 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * vp_profile_enable(ctx, 0) stops. vp_profile_read synchronises the stream and
  * returns, per phase, the summed event time in milliseconds and the number of
  * launches: phases 0..5 are the sweeps along x, y, z, vx, vy, vz, phase 6 the
- * gravity solve (density, Poisson, acceleration). Arrays have VP_NPHASE
- * entries and are caller-owned host memory. */
-#define VP_NPHASE 7
+ * gravity solve (density, Poisson, acceleration), phase 7 the one-pass half
+ * kick. Arrays have VP_NPHASE entries and are caller-owned host memory. */
+#define VP_NPHASE 8
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 

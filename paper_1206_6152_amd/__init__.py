@@ -10,12 +10,13 @@ from __future__ import annotations
 
 from . import _lib
 from ._lib import (VP_BC_ISOLATED, VP_BC_PERIODIC, VP_F32, VP_F64, VPError, make_config,
-                   vp_accel, vp_config_validate, vp_density, vp_dt, vp_energy, vp_free,
+                   vp_accel, vp_config_validate, vp_density, vp_drift, vp_dt, vp_energy, vp_free, vp_kick,
                    vp_get_accel, vp_init, vp_last_error, vp_potential, vp_profile_enable,
                    vp_profile_read, vp_run, vp_set_accel, vp_step, vp_sweep)
 
 __all__ = ["Simulator", "VPError", "make_config", "config_of", "VP_F32", "VP_F64",
            "VP_BC_PERIODIC", "VP_BC_ISOLATED", "vp_init", "vp_step", "vp_run", "vp_sweep",
+           "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential",
            "vp_energy", "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_free",
            "vp_last_error", "vp_config_validate"]
@@ -60,6 +61,12 @@ class Simulator:
 
     def sweep(self, axis: int, tau: float):
         vp_sweep(self.ctx, axis, tau)
+
+    def kick(self, tau: float):
+        vp_kick(self.ctx, tau)
+
+    def drift(self, tau: float):
+        vp_drift(self.ctx, tau)
 
     def accel(self):
         vp_accel(self.ctx)

@@ -30,10 +30,11 @@ ERROR_NAMES = {VP_EINVAL: "VP_EINVAL", VP_ENOMEM: "VP_ENOMEM", VP_EHIP: "VP_EHIP
 
 # every symbol include/vp.h declares
 EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run", "vp_sweep",
+           "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential", "vp_energy",
            "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_free", "vp_last_error"]
-VP_NPHASE = 7
-PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity"]
+VP_NPHASE = 8
+PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity", "kick"]
 
 
 class VPError(RuntimeError):
@@ -82,6 +83,8 @@ def lib():
             "vp_step": [P, f64],
             "vp_run": [P, i32, f64],
             "vp_sweep": [P, i32, f64],
+            "vp_kick": [P, f64],
+            "vp_drift": [P, f64],
             "vp_accel": [P],
             "vp_get_accel": [P, P],
             "vp_set_accel": [P, P],
@@ -148,6 +151,14 @@ def vp_run(ctx: int, nsteps: int, dt: float) -> None:
 
 def vp_sweep(ctx: int, axis: int, tau: float) -> None:
     check(lib().vp_sweep(ctx, int(axis), float(tau)))
+
+
+def vp_kick(ctx: int, tau: float) -> None:
+    check(lib().vp_kick(ctx, float(tau)))
+
+
+def vp_drift(ctx: int, tau: float) -> None:
+    check(lib().vp_drift(ctx, float(tau)))
 
 
 def vp_accel(ctx: int) -> None:

@@ -16,130 +16,225 @@
 // are, with f_inf the largest value of the line before the sweep,
 //   Lp_k = clamp(f_{k+1} - f_k, -2 (f_inf - f_k), 2 f_k),
 //   Lm_k = clamp(f_k - f_{k-1}, -2 f_k, 2 (f_inf - f_k)).
-// Transport toward decreasing index is the mirror image: the line is reversed,
-// updated as above and reversed back (the mapping is exact, also in rounding).
-// Ghost cells are zero with zero flux (outflow) or periodic images.
+// Transport toward decreasing index is the mirror image (the same update on the
+// reversed line; done by renaming registers, so it costs nothing and rounds
+// identically). Ghost cells are zero with zero flux (outflow) or periodic
+// images. Since f_k <= f_inf, the clamp bounds are always ordered, so each
+// clamp is one median-of-three.
 //
 // Execution: one lane owns one whole line in registers (the line length is a
 // template parameter). Strided axes load the line straight from HBM: lanes of a
 // wave hold adjacent lines, so every row access of the wave is one contiguous
 // segment. Contiguous lines (the vz axis) are staged through LDS so that the
-// HBM traffic stays coalesced, then transposed into registers. The alpha,
-// c1, c2 of a line are computed in FP64 and rounded once to the storage type.
+// HBM traffic stays coalesced, then transposed into registers. A half kick can
+// instead keep a spatial cell's whole velocity block in LDS and run its three
+// sweeps in one pass over HBM. The alpha, c1, c2 of a line are computed in FP64
+// and rounded once to the storage type. The whole-cell part m of the shift is
+// applied through the line's own storage (LDS row or HBM line).
 #include "vp_internal.h"
 
 namespace vp {
 namespace {
 
-template <typename T>
-__device__ __forceinline__ T vmin_(T a, T b) { return a < b ? a : b; }
-template <typename T>
-__device__ __forceinline__ T vmax_(T a, T b) { return a > b ? a : b; }
-
-// Flux F through the right face of a cell with old values (left, centre, right).
-template <typename T>
-__device__ __forceinline__ T face_flux(T fl, T f0, T fr, T finf, T alpha, T c1, T c2)
+__device__ __forceinline__ float clamp_ordered(float x, float lo, float hi)
 {
-  const T dp = fr - f0;
-  const T dm = f0 - fl;
-  const T room = finf - f0;
-  const T lp = vmin_(vmax_(dp, T(-2) * room), T(2) * f0);
-  const T lm = vmin_(vmax_(dm, T(-2) * f0), T(2) * room);
-  return alpha * (f0 + c1 * lp + c2 * lm);
+  return __builtin_amdgcn_fmed3f(x, lo, hi);
 }
-
-// Update one line held in registers by Courant number nu.
-template <typename T, int N>
-__device__ __forceinline__ void pfc_line(T (&v)[N], double nu, bool periodic)
+__device__ __forceinline__ double clamp_ordered(double x, double lo, double hi)
 {
-  const bool neg = nu < 0.0;
+  return fmin(fmax(x, lo), hi);
+}
+__device__ __forceinline__ float max_(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double max_(double a, double b) { return fmax(a, b); }
+
+template <typename T>
+struct LineCoef {
+  T alpha, c1, c2;
+  int shift;  // signed whole-cell shift s: f'_i = g_{i-s}
+  bool neg;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ LineCoef<T> line_coef(double nu, bool periodic)
+{
+  LineCoef<T> k;
+  k.neg = nu < 0.0;
   const double a = fabs(nu);
   const double fl = floor(a);
-  const double alpha_d = a - fl;
+  const double alpha = a - fl;
   int m;
   if (fl >= (double)N) m = periodic ? (int)fmod(fl, (double)N) : N;
   else m = (int)fl;
-  const T alpha = (T)alpha_d;
-  const T c1 = (T)((1.0 - alpha_d) * (2.0 - alpha_d) / 6.0);
-  const T c2 = (T)((1.0 - alpha_d) * (1.0 + alpha_d) / 6.0);
+  k.alpha = (T)alpha;
+  k.c1 = (T)((1.0 - alpha) * (2.0 - alpha) / 6.0);
+  k.c2 = (T)((1.0 - alpha) * (1.0 + alpha) / 6.0);
+  k.shift = k.neg ? -m : m;
+  return k;
+}
 
-  // mirror so that transport is toward increasing index
-#pragma unroll
-  for (int i = 0; i < N / 2; i++) {
-    const T x = v[i], y = v[N - 1 - i];
-    v[i] = neg ? y : x;
-    v[N - 1 - i] = neg ? x : y;
-  }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Fractional update g of one line held in registers, transport toward
+// increasing index of the view AT(i) = v[REV ? N-1-i : i]. Every rounding
+// step is written out (automatic contraction is off), so all kernels that use
+// this routine produce the same bits:
+//   h = 2 f_k, r = 2 f_inf - h (= 2 (f_inf - f_k) exactly),
+//   Lp = med3(f_{k+1} - f_k, -r, h), Lm = med3(f_k - f_{k-1}, -h, r),
+//   F_k = alpha * fma(c2, Lm, fma(c1, Lp, f_k)),  g_k = (f_k + F_{k-1}) - F_k.
+template <typename T, int N, bool REV>
+__device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool periodic)
+{
+#pragma clang fp contract(off)
+#define AT(i) v[REV ? (N - 1 - (i)) : (i)]
   T finf = T(0);
 #pragma unroll
-  for (int i = 0; i < N; i++) finf = vmax_(finf, v[i]);
+  for (int i = 0; i < N; i++) finf = max_(finf, v[i]);
+  const T twoinf = finf + finf;
 
-  const T ghost_l = periodic ? v[N - 1] : T(0);
-  const T ghost_r = periodic ? v[0] : T(0);
+  // flux through the left face of cell 0: zero (outflow) or that of cell N-1
   T fprev = T(0);
+  T dm = periodic ? AT(0) - AT(N - 1) : AT(0);   // f_0 - f_{-1}
   if (periodic) {
-    const T left_of_last = (N >= 2) ? v[N >= 2 ? N - 2 : 0] : v[0];
-    fprev = face_flux(left_of_last, v[N - 1], v[0], finf, alpha, c1, c2);
+    const T fl = AT(N >= 2 ? N - 2 : 0), f0 = AT(N - 1), fr = AT(0);
+    const T h = f0 + f0;
+    const T r = twoinf - h;
+    const T lp = clamp_ordered(fr - f0, -r, h);
+    const T lm = clamp_ordered(f0 - fl, -h, r);
+    fprev = alpha * fma_(c2, lm, fma_(c1, lp, f0));
   }
-  T vprev = ghost_l;
+  const T ghost_r = periodic ? AT(0) : T(0);
 #pragma unroll
   for (int i = 0; i < N; i++) {
-    const T vi = v[i];
-    const T vn = (i + 1 < N) ? v[i + 1 < N ? i + 1 : 0] : ghost_r;
-    const T F = face_flux(vprev, vi, vn, finf, alpha, c1, c2);
-    v[i] = vi + fprev - F;
+    const T f0 = AT(i);
+    const T fr = (i + 1 < N) ? AT(i + 1 < N ? i + 1 : 0) : ghost_r;
+    const T dp = fr - f0;
+    const T h = f0 + f0;
+    const T r = twoinf - h;
+    const T lp = clamp_ordered(dp, -r, h);
+    const T lm = clamp_ordered(dm, -h, r);
+    const T F = alpha * fma_(c2, lm, fma_(c1, lp, f0));
+    AT(i) = (f0 + fprev) - F;
     fprev = F;
-    vprev = vi;
+    dm = dp;
   }
+#undef AT
+}
 
-  // integer part of the shift: f'_i = g_{i-m} (wrap or zero fill)
-  if (m != 0) {
+// Fractional update of one line by Courant number nu; returns the coefficients
+// (whose shift the caller applies with apply_shift). A wave whose lines all
+// move the same way takes the matching register view; a wave with both signs
+// mirrors the negative lanes' data with selects around the forward update. All
+// routes do the same arithmetic in the same order and agree bit for bit.
+template <typename T, int N>
+__device__ __forceinline__ LineCoef<T> pfc_line(T (&v)[N], double nu, bool periodic)
+{
+  const LineCoef<T> k = line_coef<T, N>(nu, periodic);
+  const unsigned long long negs = __ballot(k.neg);
+  const unsigned long long live = __ballot(1);
+  if (negs == 0) {
+    pfc_core<T, N, false>(v, k.alpha, k.c1, k.c2, periodic);
+  } else if (negs == live) {
+    pfc_core<T, N, true>(v, k.alpha, k.c1, k.c2, periodic);
+  } else {
 #pragma unroll
-    for (int b = 1; b <= N; b <<= 1) {
-      if (m & b) {
-        T t[N];
+    for (int i = 0; i < N / 2; i++) {
+      const T x = v[i], y = v[N - 1 - i];
+      v[i] = k.neg ? y : x;
+      v[N - 1 - i] = k.neg ? x : y;
+    }
+    pfc_core<T, N, false>(v, k.alpha, k.c1, k.c2, periodic);
 #pragma unroll
-        for (int i = 0; i < N; i++) t[i] = v[i];
-#pragma unroll
-        for (int i = 0; i < N; i++) {
-          if (i - b >= 0) v[i] = t[i - b >= 0 ? i - b : 0];
-          else v[i] = periodic ? t[(i - b + N) % N >= 0 ? (i - b + N) % N : 0] : T(0);
-        }
-      }
+    for (int i = 0; i < N / 2; i++) {
+      const T x = v[i], y = v[N - 1 - i];
+      v[i] = k.neg ? y : x;
+      v[N - 1 - i] = k.neg ? x : y;
     }
   }
+  return k;
+}
 
+// f'_i = g_{i-s}: the fractional result g goes to the line's storage, then
+// each cell reads its source (periodic wrap, or zero from beyond an outflow
+// boundary). st(r, x) / ld(r) access cell r of the lane's own line.
+template <typename T, int N, typename ST, typename LD>
+__device__ __forceinline__ void apply_shift(T (&v)[N], int shift, bool periodic, ST st, LD ld)
+{
+  if (shift == 0) return;
 #pragma unroll
-  for (int i = 0; i < N / 2; i++) {
-    const T x = v[i], y = v[N - 1 - i];
-    v[i] = neg ? y : x;
-    v[N - 1 - i] = neg ? x : y;
+  for (int r = 0; r < N; r++) st(r, v[r]);
+  for (int r = 0; r < N; r++) {
+    int src = r - shift;
+    if (periodic) {
+      src %= N;
+      if (src < 0) src += N;
+    }
+    v[r] = (src >= 0 && src < N) ? ld(src) : T(0);
   }
 }
 
-__device__ __forceinline__ double line_nu(const SweepArgs& a, long long o, long long c)
+// Strided lines, general addressing: lane = line (o, c); cells at (o*N + r)*inner + c.
+__device__ __forceinline__ double line_nu_wide(const SweepArgs& a, long long o, long long c)
 {
   if (a.velocity) return a.accel[o / a.sp_div] * a.scale;
   const long long j = (c / a.j_div) % a.j_mod;
   return (a.vmin + ((double)j + 0.5) * a.dv) * a.scale;
 }
 
-// Strided lines: lane = line (o, c); cells at (o*N + r)*inner + c.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
+__global__ __launch_bounds__(256) void sweep_strided_wide(SweepArgs a)
 {
   const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
   if (gid >= a.nlines) return;
   const long long o = gid / a.inner;
   const long long c = gid - o * a.inner;
   T* p = static_cast<T*>(a.f) + o * (long long)N * a.inner + c;
+  const long long inner = a.inner;
   T v[N];
 #pragma unroll
-  for (int r = 0; r < N; r++) v[r] = p[(long long)r * a.inner];
-  pfc_line<T, N>(v, line_nu(a, o, c), a.periodic != 0);
+  for (int r = 0; r < N; r++) v[r] = p[(long long)r * inner];
+  const LineCoef<T> k = pfc_line<T, N>(v, line_nu_wide(a, o, c), a.periodic != 0);
+  apply_shift<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { p[(long long)r * inner] = x; },
+                    [&](int r) { return p[(long long)r * inner]; });
 #pragma unroll
-  for (int r = 0; r < N; r++) p[(long long)r * a.inner] = v[r];
+  for (int r = 0; r < N; r++) p[(long long)r * inner] = v[r];
+}
+
+// Strided lines, compact addressing: the workgroup's first line is the uniform
+// base; a lane's cells sit at base + r*inner + off with a 32-bit offset (the
+// host checks that every offset fits), and the line index arithmetic is 32-bit.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
+{
+  const long long gid0 = (long long)blockIdx.x * 256;
+  const unsigned t = threadIdx.x;
+  if (gid0 + t >= a.nlines) return;
+  const long long o0 = gid0 / a.inner;
+  const unsigned inner = (unsigned)a.inner;
+  const unsigned c0 = (unsigned)(gid0 - o0 * a.inner);
+  const unsigned cc = c0 + t;
+  const unsigned dov = cc / inner;          // slabs past the base line's slab
+  const unsigned c = cc - dov * inner;
+  const unsigned off = dov * (unsigned)(N * inner) + c - c0;
+  T* fb = static_cast<T*>(a.f) + (o0 * N * (long long)inner + c0);
+  double nu;
+  if (a.velocity) {
+    const long long sp_div = a.sp_div;
+    const long long q0 = o0 / sp_div;
+    const unsigned r0 = (unsigned)(o0 - q0 * sp_div);
+    nu = a.accel[q0 + (r0 + dov) / (unsigned)sp_div] * a.scale;
+  } else {
+    const unsigned j = (c / (unsigned)a.j_div) % (unsigned)a.j_mod;
+    nu = (a.vmin + ((double)j + 0.5) * a.dv) * a.scale;
+  }
+  T v[N];
+#pragma unroll
+  for (int r = 0; r < N; r++) v[r] = (fb + (long long)r * inner)[off];
+  const LineCoef<T> k = pfc_line<T, N>(v, nu, a.periodic != 0);
+  apply_shift<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { (fb + (long long)r * inner)[off] = x; },
+                    [&](int r) { return (fb + (long long)r * inner)[off]; });
+#pragma unroll
+  for (int r = 0; r < N; r++) (fb + (long long)r * inner)[off] = v[r];
 }
 
 template <typename T, int N>
@@ -214,14 +309,24 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
     const int count = nl * N;
     for (int e = tid; e < count; e += LINES) tile[(e / N) * P + (e % N)] = g[e];
   }
+  double nu;
+  if (a.velocity) {
+    const long long q0 = line0 / a.sp_div;
+    const unsigned r0 = (unsigned)(line0 - q0 * a.sp_div);
+    nu = a.accel[q0 + (r0 + (unsigned)tid) / (unsigned)a.sp_div] * a.scale;
+  } else {
+    nu = (a.vmin + 0.5 * a.dv) * a.scale;   // inner == 1: one velocity cell on this axis
+  }
   __syncthreads();
   if (tid < nl) {
+    T* row = tile + tid * P;
     T v[N];
 #pragma unroll
-    for (int r = 0; r < N; r++) v[r] = tile[tid * P + r];
-    pfc_line<T, N>(v, line_nu(a, line0 + tid, 0), a.periodic != 0);
+    for (int r = 0; r < N; r++) v[r] = row[r];
+    const LineCoef<T> k = pfc_line<T, N>(v, nu, a.periodic != 0);
+    apply_shift<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { row[r] = x; }, [&](int r) { return row[r]; });
 #pragma unroll
-    for (int r = 0; r < N; r++) tile[tid * P + r] = v[r];
+    for (int r = 0; r < N; r++) row[r] = v[r];
   }
   __syncthreads();
   if (nl == LINES) {
@@ -249,6 +354,127 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
   }
 }
 
+// ---- one-pass half kick -----------------------------------------------------
+// The velocity block of one spatial cell (NX*NY*NZ values, contiguous in HBM)
+// is read once into LDS, swept along vx, then vy, then vz (each lane owns one
+// line per sweep, in registers), and written back once. The LDS layout pads
+// each vz row to NZ+1 and each vx plane to SX = NZ (mod 64) elements, which
+// keeps the accesses of all three sweep directions on distinct banks.
+template <typename T, int NX, int NY, int NZ>
+struct KickShape {
+  static constexpr int SY = NZ + 1;
+  static constexpr int SX0 = NY * SY;
+  static constexpr int SX = SX0 + ((((NZ - SX0) % 64) + 64) % 64);
+  static constexpr int ELEMS = NX * SX;
+  static constexpr int BYTES = ELEMS * (int)sizeof(T);
+  static constexpr int L0 = NY * NZ, L1 = NX * NZ, L2 = NX * NY;
+  static constexpr int LINES = L0 > L1 ? (L0 > L2 ? L0 : L2) : (L1 > L2 ? L1 : L2);
+  static constexpr int THREADS = ((LINES + 63) / 64) * 64;
+  static constexpr int NV3 = NX * NY * NZ;
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && (NV3 % (16 / (int)sizeof(T))) == 0;
+};
+
+template <typename T, int NX, int NY, int NZ>
+__device__ __forceinline__ int kick_lds_index(int e)
+{
+  using S = KickShape<T, NX, NY, NZ>;
+  const int jz = e % NZ;
+  const int jy = (e / NZ) % NY;
+  const int jx = e / (NY * NZ);
+  return jx * S::SX + jy * S::SY + jz;
+}
+
+template <typename T, int NX, int NY, int NZ>
+__global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_block(KickArgs a)
+{
+  using S = KickShape<T, NX, NY, NZ>;
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::n;
+  constexpr int NVEC = S::NV3 / V;
+  constexpr int PER = (NVEC + S::THREADS - 1) / S::THREADS;
+  __shared__ T L[S::ELEMS];
+  const int tid = threadIdx.x;
+  const long long s = blockIdx.x;
+  VT* g = reinterpret_cast<VT*>(static_cast<T*>(a.f) + s * S::NV3);
+
+  {
+    VT x[PER];
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = tid + k * S::THREADS;
+      if (i < NVEC) x[k] = g[i];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = tid + k * S::THREADS;
+      if (i < NVEC) {
+#pragma unroll
+        for (int q = 0; q < V; q++) L[kick_lds_index<T, NX, NY, NZ>(i * V + q)] = lane_of<VT, T>(x[k], q);
+      }
+    }
+  }
+  const double nux = a.a[0][s] * a.scale[0];
+  const double nuy = a.a[1][s] * a.scale[1];
+  const double nuz = a.a[2][s] * a.scale[2];
+  __syncthreads();
+  if (tid < S::L0) {  // vx lines: (jy, jz)
+    const int base = (tid / NZ) * S::SY + (tid % NZ);
+    T v[NX];
+#pragma unroll
+    for (int r = 0; r < NX; r++) v[r] = L[base + r * S::SX];
+    const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
+    apply_shift<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; },
+                       [&](int r) { return L[base + r * S::SX]; });
+#pragma unroll
+    for (int r = 0; r < NX; r++) L[base + r * S::SX] = v[r];
+  }
+  __syncthreads();
+  if (tid < S::L1) {  // vy lines: (jx, jz)
+    const int base = (tid / NZ) * S::SX + (tid % NZ);
+    T v[NY];
+#pragma unroll
+    for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
+    const LineCoef<T> k = pfc_line<T, NY>(v, nuy, false);
+    apply_shift<T, NY>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; },
+                       [&](int r) { return L[base + r * S::SY]; });
+#pragma unroll
+    for (int r = 0; r < NY; r++) L[base + r * S::SY] = v[r];
+  }
+  __syncthreads();
+  if (tid < S::L2) {  // vz lines: (jx, jy)
+    const int base = (tid / NY) * S::SX + (tid % NY) * S::SY;
+    T v[NZ];
+#pragma unroll
+    for (int r = 0; r < NZ; r++) v[r] = L[base + r];
+    const LineCoef<T> k = pfc_line<T, NZ>(v, nuz, false);
+    apply_shift<T, NZ>(v, k.shift, false, [&](int r, T x) { L[base + r] = x; }, [&](int r) { return L[base + r]; });
+#pragma unroll
+    for (int r = 0; r < NZ; r++) L[base + r] = v[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = tid + k * S::THREADS;
+    if (i < NVEC) {
+      VT x;
+      T* xs = reinterpret_cast<T*>(&x);
+#pragma unroll
+      for (int q = 0; q < V; q++) xs[q] = L[kick_lds_index<T, NX, NY, NZ>(i * V + q)];
+      g[i] = x;
+    }
+  }
+}
+
+template <typename T, int NV>
+hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
+{
+  using S = KickShape<T, NV, NV, NV>;
+  static_assert(S::fits, "velocity block does not fit the LDS");
+  if (a.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL((kick_block<T, NV, NV, NV>), dim3((unsigned)a.np), dim3(S::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int N>
 hipError_t launch_n(const SweepArgs& a, hipStream_t s)
 {
@@ -259,7 +485,16 @@ hipError_t launch_n(const SweepArgs& a, hipStream_t s)
     hipLaunchKernelGGL((sweep_contig<T, N>), dim3((unsigned)blocks), dim3(LINES), 0, s, a);
   } else {
     const long long blocks = (a.nlines + 255) / 256;
-    hipLaunchKernelGGL((sweep_strided<T, N>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    // compact addressing when every lane offset from its workgroup's first
+    // line fits in 31 bits and the index arithmetic fits in 32 bits
+    const bool no_straddle = (a.inner % 256) == 0;
+    const long long span = no_straddle ? 256 : (256 / a.inner + 2) * (long long)N * a.inner;
+    const bool narrow = a.inner < (1LL << 31) && span < (1LL << 31) && a.j_div < (1LL << 31) &&
+                        a.j_mod < (1LL << 31) && a.sp_div < (1LL << 31);
+    if (narrow)
+      hipLaunchKernelGGL((sweep_strided<T, N>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((sweep_strided_wide<T, N>), dim3((unsigned)blocks), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -302,6 +537,34 @@ bool sweep_length_supported(int n)
 hipError_t launch_sweep(const SweepArgs& a, int dtype, hipStream_t s)
 {
   return dtype == 0 ? launch_t<float>(a, s) : launch_t<double>(a, s);
+}
+
+// Velocity cubes whose block fits the LDS of one workgroup: FP32 up to 32^3,
+// FP64 up to 24^3.
+bool kick_fused_supported(int dtype, const int nv[3])
+{
+  if (nv[0] != nv[1] || nv[1] != nv[2]) return false;
+  const int n = nv[0];
+  if (dtype == 0) return n == 8 || n == 16 || n == 24 || n == 32;
+  return n == 8 || n == 16 || n == 24;
+}
+
+hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)
+{
+  if (!kick_fused_supported(dtype, nv)) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    switch (nv[0]) {
+      case 8: return launch_kick_cube<float, 8>(a, s);
+      case 16: return launch_kick_cube<float, 16>(a, s);
+      case 24: return launch_kick_cube<float, 24>(a, s);
+      default: return launch_kick_cube<float, 32>(a, s);
+    }
+  }
+  switch (nv[0]) {
+    case 8: return launch_kick_cube<double, 8>(a, s);
+    case 16: return launch_kick_cube<double, 16>(a, s);
+    default: return launch_kick_cube<double, 24>(a, s);
+  }
 }
 
 }  // namespace vp

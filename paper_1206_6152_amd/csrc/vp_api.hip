@@ -67,8 +67,8 @@ struct vp_ctx {
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-  double phase_ms[VP_NPHASE] = {0, 0, 0, 0, 0, 0, 0};
-  long long phase_n[VP_NPHASE] = {0, 0, 0, 0, 0, 0, 0};
+  double phase_ms[VP_NPHASE] = {};
+  long long phase_n[VP_NPHASE] = {};
 };
 
 namespace {
@@ -253,6 +253,34 @@ int sweep(vp_ctx* c, int axis, double tau)
   return VP_OK;
 }
 
+// T_vz T_vy T_vx(tau): one pass when the velocity block fits on chip.
+int kick(vp_ctx* c, double tau)
+{
+  const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
+  if (vp::kick_fused_supported(c->cfg.dtype, nv)) {
+    vp::KickArgs a{};
+    a.f = c->f;
+    a.np = c->np;
+    for (int l = 0; l < 3; l++) {
+      a.a[l] = c->accel + (long long)l * c->np;
+      a.scale[l] = tau / c->dv[l];
+    }
+    PhaseScope scope(c, 7);
+    LAUNCH(c, vp::launch_kick(a, c->cfg.dtype, nv, c->stream));
+    return VP_OK;
+  }
+  int r;
+  if ((r = sweep(c, 3, tau)) || (r = sweep(c, 4, tau)) || (r = sweep(c, 5, tau))) return r;
+  return VP_OK;
+}
+
+int drift(vp_ctx* c, double tau)
+{
+  int r;
+  if ((r = sweep(c, 2, tau)) || (r = sweep(c, 1, tau)) || (r = sweep(c, 0, tau))) return r;
+  return VP_OK;
+}
+
 int check_ctx(vp_ctx* c)
 {
   if (!c) return fail(VP_EINVAL, "null context");
@@ -389,10 +417,7 @@ int vp_step(vp_ctx* c, double dt)
   if (r) return r;
   if (!(std::isfinite(dt) && dt > 0)) return fail(VP_EINVAL, "dt must be finite and > 0");
   const double h = 0.5 * dt;
-  if ((r = sweep(c, 3, h)) || (r = sweep(c, 4, h)) || (r = sweep(c, 5, h))) return r;
-  if ((r = sweep(c, 2, dt)) || (r = sweep(c, 1, dt)) || (r = sweep(c, 0, dt))) return r;
-  if ((r = compute_accel(c))) return r;
-  if ((r = sweep(c, 3, h)) || (r = sweep(c, 4, h)) || (r = sweep(c, 5, h))) return r;
+  if ((r = kick(c, h)) || (r = drift(c, dt)) || (r = compute_accel(c)) || (r = kick(c, h))) return r;
   return VP_OK;
 }
 
@@ -406,6 +431,24 @@ int vp_run(vp_ctx* c, int32_t nsteps, double dt)
   for (int i = 0; i < nsteps; i++)
     if ((r = vp_step(c, dt))) return r;
   return VP_OK;
+}
+
+int vp_kick(vp_ctx* c, double tau)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
+  return kick(c, tau);
+}
+
+int vp_drift(vp_ctx* c, double tau)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
+  return drift(c, tau);
 }
 
 int vp_accel(vp_ctx* c)

@@ -33,6 +33,20 @@ hipError_t launch_sweep(const SweepArgs& a, int dtype, hipStream_t s);
 // True when n is a line length the sweep kernels are instantiated for.
 bool sweep_length_supported(int n);
 
+// Half kick T_vz T_vy T_vx(tau) of every spatial cell's velocity block in one
+// pass: the block of cell s is f[s*nv3 .. (s+1)*nv3) and moves with
+// nu_l = a_l[s] * scale_l.
+struct KickArgs {
+  void* f;
+  long long np;
+  const double* a[3];
+  double scale[3];
+};
+
+// True when a one-pass kernel exists for this velocity grid and element type.
+bool kick_fused_supported(int dtype, const int nv[3]);
+hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
+
 // ---- gravity and reductions (FP64) ----------------------------------------
 
 // rho[s] = dv3 * sum_j f[s*nv3 + j]
