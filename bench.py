@@ -75,6 +75,38 @@ def copy_bandwidth(f):
     return nbytes / (ms * 1e-3) / 1e9
 
 
+def committed_traffic(w, elem_bytes, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md"
+                        % (w.name.replace("_", ""), "f32" if elem_bytes == 4 else "f64"))
+    if not os.path.exists(path):
+        return None
+    digests, traffic = {}, {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "sha256":
+            digests[parts[2]] = parts[1]
+        elif len(parts) >= 3 and parts[0] == "traffic_bytes":
+            traffic[" ".join(parts[1:-1])] = float(parts[-1])
+    for rel, digest in digests.items():
+        cur = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()
+        if cur != digest:
+            return None
+    return traffic.get(kernel)
+
+
+def kernel_name(phase, w, elem_bytes):
+    t = "float" if elem_bytes == 4 else "double"
+    if phase == "kick":
+        return "vp::kick_block<%s, %d, %d, %d>" % (t, w.nv[0], w.nv[1], w.nv[2])
+    axis = ["x", "y", "z", "vx", "vy", "vz"].index(phase)
+    n = (list(w.n) + list(w.nv))[axis]
+    kind = "sweep_contig" if axis == 5 else "sweep_strided"
+    return "vp::%s<%s, %d>" % (kind, t, n)
+
+
 def gpu_run(w, vp_dtype, steps, warmup):
     import torch
     from paper_1206_6152_amd import VP_F32, Simulator, config_of
@@ -108,6 +140,8 @@ def gpu_run(w, vp_dtype, steps, warmup):
     achieved = sweep_bytes / (dom_ms * 1e-3) / 1e9
     step_ms = wall * 1e3 / steps
     step_bytes = 19.0 * s * cells          # 9 sweeps x 2 + one density read
+    kname = kernel_name(dom, w, s)
+    traffic = committed_traffic(w, s, kname)
     return dict(
         value=cells * steps / wall,
         ms_per_step=step_ms,
@@ -116,7 +150,8 @@ def gpu_run(w, vp_dtype, steps, warmup):
         roofline=dict(bound="hbm", kernel=("one-pass half kick (vx, vy, vz sweeps)" if dom == "kick"
                                            else "pfc sweep along %s" % dom), achieved=achieved,
                       peak=PEAK_HBM_GBPS, unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
-                      traffic=None, algorithmic_bytes_per_launch=sweep_bytes,
+                      traffic=traffic, traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
+                      "copy-calibrated)", hip_kernel=kname, algorithmic_bytes_per_launch=sweep_bytes,
                       avg_launch_ms=dom_ms),
         step_roofline=dict(model_bytes_per_step=step_bytes,
                            achieved_GBps=step_bytes / (step_ms * 1e-3) / 1e9,
