@@ -1,0 +1,174 @@
+"""Full-size GPU checks, in the launch configurations the benchmark uses.
+
+The oracle cannot hold these grids, so outputs are checked where it can compute
+them one by one: every sweep line depends only on its own input line and one
+Courant number, and a half kick of one spatial cell depends only on that
+cell's velocity block and acceleration. Sampled lines and blocks are copied
+out before and after the GPU call and compared with the oracle's line and
+sweep operators. A full step is then checked for properties that hold at any
+size: mass conservation (periodic space, wide velocity box), positivity and a
+finite energy."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_l1
+from paper_1206_6152_amd import VP_F32, VP_F64, Simulator, config_of, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def device_f(w, dtype):
+    """f on the device (FP64 product, rounded once), as the benchmark builds it."""
+    torch = _torch()
+    tdt = torch.float32 if dtype == VP_F32 else torch.float64
+    dev = torch.device("cuda:0")
+    if w.bc == 1:
+        psi = torch.from_numpy(inputs.king_psi(w).reshape(-1)).to(dev)
+        V = np.meshgrid(*[w.vc(l) for l in range(3)], indexing="ij")
+        half_v2 = torch.from_numpy((0.5 * (V[0] ** 2 + V[1] ** 2 + V[2] ** 2)).reshape(-1)).to(dev)
+        pref = inputs.king_prefactor(w.params["W0"])
+        f = torch.empty(w.shape, dtype=tdt, device=dev)
+        fv = f.view(psi.numel(), half_v2.numel())
+        for i in range(0, psi.numel(), 512):
+            e = psi[i:i + 512, None] - half_v2[None, :]
+            fv[i:i + 512] = torch.where(e > 0, pref * torch.expm1(e.clamp(min=0)), torch.zeros_like(e)).to(tdt)
+        torch.cuda.synchronize()
+        return f
+    dens, m = inputs.separable_factors(w)
+    d = torch.from_numpy(dens.reshape(-1)).to(dev)
+    mv = torch.from_numpy(m.reshape(-1)).to(dev)
+    f = torch.empty(w.shape, dtype=tdt, device=dev)
+    fv = f.view(d.numel(), mv.numel())
+    step = max(1, (1 << 27) // mv.numel())
+    for i in range(0, d.numel(), step):
+        fv[i:i + step] = (d[i:i + step, None] * mv[None, :]).to(tdt)
+    torch.cuda.synchronize()
+    return f
+
+
+def sample_lines(w, axis, count, seed):
+    """index tuples (6D with a slice on `axis`) of sampled lines"""
+    rng = np.random.default_rng(seed)
+    shape = w.shape
+    out = []
+    for _ in range(count):
+        idx = [int(rng.integers(0, s)) for s in shape]
+        idx[axis] = slice(None)
+        out.append(tuple(idx))
+    return out
+
+
+def _check_sweep(sim, f, w, dtype, axis, tau, seed, fscale, count=48):
+    lines = sample_lines(w, axis, count, seed)
+    before = [f[i].double().cpu().numpy() for i in lines]
+    a = sim.get_accel().cpu().numpy() if axis >= 3 else None
+    sim.sweep(axis, tau)
+    after = [f[i].double().cpu().numpy() for i in lines]
+    periodic = axis < 3 and w.bc == 0
+    # errors are measured on the scale of the field (its largest value), the
+    # scale of the relative-L1 parity norm; lines far out in a Maxwellian tail
+    # hold values many orders below it (down to FP32 subnormals)
+    scale = fscale
+    worst, worst_line, l1_err, l1_ref = 0.0, None, 0.0, 0.0
+    for i, b, g in zip(lines, before, after):
+        if axis < 3:
+            j = i[axis + 3]
+            nu = (w.vmin[axis] + (j + 0.5) * w.dv(axis)) * tau / w.dx(axis)
+        else:
+            nu = a[axis - 3][i[0], i[1], i[2]] * tau / w.dv(axis - 3)
+        ref = oracle.line(b, nu, periodic)
+        e = np.abs(g - ref).max() / scale
+        l1_err += np.abs(g - ref).sum()
+        l1_ref += np.abs(ref).sum()
+        if e > worst:
+            worst, worst_line = e, (i, float(np.abs(b).max()))
+    print("axis", axis, "max err / max f", worst, "line", worst_line, flush=True)
+    tol = 1e-13 if dtype == VP_F64 else 3e-6
+    assert worst <= tol, (axis, worst, worst_line)
+    if l1_ref > 0:
+        assert l1_err / l1_ref <= (1e-14 if dtype == VP_F64 else 1e-6)
+    return worst
+
+
+def _check_kick(sim, f, w, dtype, tau, seed, count=6):
+    rng = np.random.default_rng(seed)
+    cells = [tuple(int(rng.integers(0, n)) for n in w.n) for _ in range(count)]
+    before = [f[c].double().cpu().numpy() for c in cells]
+    a = sim.get_accel().cpu().numpy()
+    sim.kick(tau)
+    after = [f[c].double().cpu().numpy() for c in cells]
+    g = oracle.Grid(n=(1, 1, 1), nv=w.nv, L=(1.0, 1.0, 1.0), vmin=w.vmin, vmax=w.vmax, G=w.G, bc=w.bc)
+    for c, b, out in zip(cells, before, after):
+        acc = np.array([a[l][c] for l in range(3)]).reshape(3, 1, 1, 1)
+        ref = b.reshape((1, 1, 1) + w.nv)
+        for ax in (3, 4, 5):
+            ref = oracle.sweep(g, ref, ax, tau, acc)
+        err = rel_l1(out, ref[0, 0, 0])
+        assert err <= (1e-14 if dtype == VP_F64 else 2e-6), (c, err)
+
+
+WORKLOADS = [("jeans_32x32", VP_F32), ("jeans_32x32", VP_F64), ("king_w6_48x48", VP_F32),
+             ("slab_16x64x64_64", VP_F32)]
+
+
+@pytest.mark.parametrize("name,dtype", WORKLOADS)
+def test_full_size_sweeps_and_kick_sampled(name, dtype):
+    print("workload", name, "dtype", dtype, flush=True)
+    torch = _torch()
+    w = inputs.WORKLOADS[name]()
+    f = device_f(w, dtype)
+    sim = Simulator(config_of(w, dtype), f)
+    dt = w.dt if w.dt > 0 else sim.dt(0.5)
+    fscale = float(f.abs().max())
+    print("dt", dt, "max f", fscale, flush=True)
+    for axis in (2, 1, 0):
+        _check_sweep(sim, f, w, dtype, axis, dt, seed=axis, fscale=fscale)
+    for axis in (3, 4, 5):
+        _check_sweep(sim, f, w, dtype, axis, 0.5 * dt, seed=10 + axis, fscale=fscale)
+    _check_kick(sim, f, w, dtype, 0.5 * dt, seed=20)
+    sim.close()
+    del f
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name,dtype", WORKLOADS)
+def test_full_size_step_properties(name, dtype):
+    print("workload", name, "dtype", dtype, flush=True)
+    torch = _torch()
+    w = inputs.WORKLOADS[name]()
+    f = device_f(w, dtype)
+    sim = Simulator(config_of(w, dtype), f)
+    dt = w.dt if w.dt > 0 else sim.dt(0.5)
+    K0, U0, M0, E0 = sim.energy()
+    sim.run(2, dt)
+    K1, U1, M1, E1 = sim.energy()
+    fmin = float(f.min())
+    fmax0 = float(f.max())
+    print("mass drift", (M1 - M0) / M0, "energy drift", (E1 - E0) / abs(E0), "min f", fmin, flush=True)
+    assert math.isfinite(E1)
+    assert fmin >= -1e-6 * fmax0
+    if w.bc == 0:
+        # periodic space; only the Maxwellian tail beyond the velocity box can leave
+        assert abs(M1 - M0) / M0 < (1e-6 if dtype == VP_F32 else 1e-8)
+    else:
+        # King sphere inside the escape speed: mass stays within the box for two steps
+        assert abs(M1 - M0) / M0 < 1e-4
+    # the density the library reports equals the velocity sum of the stored f
+    rho = sim.density().cpu().numpy()
+    cells = [(0, 0, 0), tuple(x // 2 for x in w.n), tuple(x - 1 for x in w.n)]
+    dv3 = w.dv(0) * w.dv(1) * w.dv(2)
+    for c in cells:
+        blk = f[c].double().cpu().numpy()
+        assert rho[c] == pytest.approx(blk.sum() * dv3, rel=1e-12, abs=1e-300)
+    sim.close()
+    del f
+    torch.cuda.empty_cache()

@@ -137,3 +137,27 @@ def test_velocity_line_lengths_of_the_workloads(nvl, dtype):
         out = gpu_sweep(w, f0, dtype, axis, tau, accel)
         tol = 1e-14 if dtype == VP_F64 else 1e-6
         assert rel_l1(out, ref) <= tol, axis
+
+
+@pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
+@pytest.mark.parametrize("nl", [24, 32, 48, 64, 96, 128])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+def test_position_line_lengths_of_the_workloads(nl, bc, dtype):
+    # position lines of the workloads' lengths along z (mixed-sign waves), y
+    # and x, periodic and outflow
+    w = small_workload(bc, n=(nl, 2, nl), nv=(2, 3, 4))
+    w = inputs.Workload(name="pos", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
+                        vmax=(1.5, 2.0, 1.5), G=1.0, bc=bc)
+    f0 = structured_f(w.shape, seed=nl + bc).astype(NP[dtype]).astype(np.float64)
+    g = oracle_grid(w)
+    for axis in (2, 0):
+        vmax = max(abs(w.vmin[axis]), abs(w.vmax[axis]))
+        tau = 0.8 * w.dx(axis) / vmax
+        ref = oracle.sweep(g, f0, axis, tau, np.zeros((3,) + w.n))
+        out = gpu_sweep(w, f0, dtype, axis, tau, None)
+        err = np.abs(out - ref).max() / np.abs(f0).max()
+        if err > (1e-13 if dtype == VP_F64 else 3e-6):
+            bad = np.argwhere(np.abs(out - ref) > (1e-13 if dtype == VP_F64 else 3e-6) * np.abs(f0).max())
+            print("axis", axis, "max err", err, "bad count", len(bad), "first", bad[:8].tolist(), flush=True)
+        tol = 1e-14 if dtype == VP_F64 else 1e-6
+        assert rel_l1(out, ref) <= tol, (axis, rel_l1(out, ref))
