@@ -73,6 +73,14 @@ def _load():
             lib.oracle_cell_self_integral.argtypes = [ctypes.c_double] * 3
             lib.oracle_cell_self_integral.restype = ctypes.c_double
             lib.oracle_num_threads.restype = ctypes.c_int
+            lib.oracle_line_vjp.argtypes = [_D, ctypes.c_int, ctypes.c_double, ctypes.c_int, _D, _D]
+            lib.oracle_line_vjp.restype = ctypes.c_double
+            lib.oracle_sweep_vjp.argtypes = [P, _D, ctypes.c_int, ctypes.c_double, _D, _D, _D]
+            lib.oracle_accel_vjp.argtypes = [P, _D, _D]
+            lib.oracle_grad.argtypes = [P, _D, ctypes.c_int, ctypes.c_double, _D]
+            lib.oracle_grad.restype = ctypes.c_double
+            lib.oracle_field_energy_loss.argtypes = [P, _D]
+            lib.oracle_field_energy_loss.restype = ctypes.c_double
             _lib = lib
     return _lib
 
@@ -210,6 +218,63 @@ def cell_self_integral(dx: float, dy: float, dz: float) -> float:
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def line_vjp(f, nu: float, periodic: bool, lam_out):
+    """(lam_f, dL/dnu) for the line update: lam_f = J^T lam_out."""
+    lib = _load()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lo = np.ascontiguousarray(lam_out, dtype=np.float64)
+    lf = np.zeros_like(f)
+    dnu = lib.oracle_line_vjp(_ptr(f), f.size, float(nu), int(periodic), _ptr(lo), _ptr(lf))
+    return lf, float(dnu)
+
+
+def sweep_vjp(g: Grid, f_in, axis: int, tau: float, lam, accel=None):
+    """(J^T lam, lam_accel contribution) of T_axis(tau) at input f_in."""
+    lib = _load()
+    f_in = np.ascontiguousarray(f_in, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64).copy()
+    la = np.zeros((3,) + tuple(g.n))
+    c = g.cstruct()
+    a = np.ascontiguousarray(accel if accel is not None else np.zeros((3,) + tuple(g.n)), dtype=np.float64)
+    lib.oracle_sweep_vjp(ctypes.byref(c), _ptr(f_in), axis, float(tau), _ptr(a), _ptr(lam), _ptr(la))
+    return lam, la
+
+
+def accel_vjp(g: Grid, lam_accel, nv_shape=None):
+    """dv3 * (G^T D^T lam_accel) broadcast over velocity, shape of f."""
+    lib = _load()
+    la = np.ascontiguousarray(lam_accel, dtype=np.float64)
+    out = np.zeros(g.shape)
+    c = g.cstruct()
+    lib.oracle_accel_vjp(ctypes.byref(c), _ptr(la), _ptr(out))
+    return out
+
+
+def grad(g: Grid, f0, nsteps: int, dt_: float):
+    """(L, dL/df0) with L = -U after nsteps steps (fixed dt)."""
+    lib = _load()
+    f0 = np.ascontiguousarray(f0, dtype=np.float64)
+    out = np.zeros_like(f0)
+    c = g.cstruct()
+    L = lib.oracle_grad(ctypes.byref(c), _ptr(f0), int(nsteps), float(dt_), _ptr(out))
+    return float(L), out
+
+
+def field_energy_loss(g: Grid, f) -> float:
+    lib = _load()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    c = g.cstruct()
+    return float(lib.oracle_field_energy_loss(ctypes.byref(c), _ptr(f)))
+
+
+def run_loss(g: Grid, f0, nsteps: int, dt_: float) -> float:
+    """L = -U after nsteps steps from f0 (forward only)."""
+    r = Run(g, f0)
+    for _ in range(nsteps):
+        r.step(dt_)
+    return field_energy_loss(g, r.f)
 
 
 @dataclass

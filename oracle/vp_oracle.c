@@ -524,3 +524,302 @@ int oracle_num_threads(void)
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* reverse mode (gradient of the field energy; not in the paper)      */
+/* ------------------------------------------------------------------ */
+/*
+ * The loss is L = -U of the final state (U of Eq. (41)), a function of the
+ * initial f through nsteps steps of Eq. (17) with a fixed dt. The reverse mode
+ * below is written against this file's own forward definitions:
+ *   - the line update is the integral of the limited profile over the
+ *     traced-back interval, out_i = sum over crossed cells k of
+ *     c_k w0 + lp_k w1 - lm_k w2 with weights that depend only on nu; its
+ *     adjoint sends lam_out through those weights to (c, lp, lm), then through
+ *     the corrector branch that is active (a corrector that bounds the slope
+ *     by 2 f_k or by 2 (f_inf - f_k) passes the adjoint to f_k and to f_inf),
+ *     and f_inf passes its adjoint to the first cell holding the maximum;
+ *   - the derivative in nu is the Leibniz rule at the two ends of the
+ *     traced-back interval: d out_i / d nu = f_h(left end) - f_h(right end);
+ *   - a velocity sweep's nu = a_l(x) tau / dv_l carries the adjoint to a_l;
+ *   - the acceleration, potential and density are linear; their transposes
+ *     are written out (the periodic operator and the isolated convolution
+ *     are symmetric).
+ * Branch convention at exact ties: a corrector bound is active only when the
+ * one-sided difference is strictly beyond it.
+ */
+
+static double profile_value(double c, double lp, double lm, double s)
+{
+  return c + lp * (3.0 * s * s + 3.0 * s - 0.25) / 6.0 - lm * (3.0 * s * s - 3.0 * s - 0.25) / 6.0;
+}
+
+static long wrap_index(long k, int n) { long m = k % n; return m < 0 ? m + n : m; }
+
+/* Adjoint of oracle_line: lam_f += J^T lam_out (J = d out / d f); returns
+ * sum_i lam_out_i d out_i / d nu. */
+double oracle_line_vjp(const double *f, int n, double nu, int periodic, const double *lam_out, double *lam_f)
+{
+  double finf = 0.0;
+  int amax = -1;
+  for (int i = 0; i < n; i++)
+    if (f[i] > finf) { finf = f[i]; amax = i; }
+  double *lc = (double *)calloc(n, sizeof(double));
+  double *lp_ = (double *)calloc(n, sizeof(double));
+  double *lm_ = (double *)calloc(n, sizeof(double));
+  double dnu = 0.0;
+  for (int i = 0; i < n; i++) {
+    if (lam_out[i] == 0.0) continue;
+    double a = (double)i - 0.5 - nu;
+    double b = (double)i + 0.5 - nu;
+    long k0 = (long)floor(a + 0.5);
+    long k1 = (long)floor(b + 0.5);
+    for (long k = k0; k <= k1; k++) {
+      double lo = fmax(a, (double)k - 0.5);
+      double hi = fmin(b, (double)k + 0.5);
+      if (!(hi > lo)) continue;
+      if (!periodic && (k < 0 || k >= n)) continue;   /* zero profile */
+      long kk = periodic ? wrap_index(k, n) : k;
+      double s0 = lo - (double)k, s1 = hi - (double)k;
+      double c, lp, lm;
+      cell_profile(f, n, k, periodic, finf, 1, &c, &lp, &lm);
+      lc[kk] += lam_out[i] * (s1 - s0);
+      lp_[kk] += lam_out[i] * (anti_p(s1) - anti_p(s0)) / 6.0;
+      lm_[kk] -= lam_out[i] * (anti_q(s1) - anti_q(s0)) / 6.0;
+      if (lo == a) dnu += lam_out[i] * profile_value(c, lp, lm, s0);
+      if (hi == b) dnu -= lam_out[i] * profile_value(c, lp, lm, s1);
+    }
+  }
+  double lfinf = 0.0;
+  for (int k = 0; k < n; k++) {
+    double fk = f[k];
+    long kr = k + 1, kl = k - 1;
+    int has_r = periodic || kr < n, has_l = periodic || kl >= 0;
+    double fr = has_r ? f[periodic ? wrap_index(kr, n) : kr] : 0.0;
+    double fl = has_l ? f[periodic ? wrap_index(kl, n) : kl] : 0.0;
+    lam_f[k] += lc[k];
+    /* lp = eps+ (f_{k+1} - f_k) */
+    double dp = fr - fk, g = lp_[k];
+    if (dp > 0.0 && 2.0 * fk < dp) {
+      lam_f[k] += 2.0 * g;
+    } else if (dp < 0.0 && 2.0 * (finf - fk) < -dp) {
+      lfinf -= 2.0 * g;
+      lam_f[k] += 2.0 * g;
+    } else {
+      if (has_r) lam_f[periodic ? wrap_index(kr, n) : kr] += g;
+      lam_f[k] -= g;
+    }
+    /* lm = eps- (f_k - f_{k-1}) */
+    double dm = fk - fl;
+    g = lm_[k];
+    if (dm > 0.0 && 2.0 * (finf - fk) < dm) {
+      lfinf += 2.0 * g;
+      lam_f[k] -= 2.0 * g;
+    } else if (dm < 0.0 && 2.0 * fk < -dm) {
+      lam_f[k] -= 2.0 * g;
+    } else {
+      lam_f[k] += g;
+      if (has_l) lam_f[periodic ? wrap_index(kl, n) : kl] -= g;
+    }
+  }
+  if (amax >= 0) lam_f[amax] += lfinf;
+  free(lc);
+  free(lp_);
+  free(lm_);
+  return dnu;
+}
+
+/* Adjoint of oracle_sweep at input state f_in: lam <- J^T lam; for velocity
+ * axes lam_accel[axis-3][x] += (tau / dv) * (sum over the cell's lines of the
+ * nu-adjoint). */
+void oracle_sweep_vjp(const oracle_cfg *c, const double *f_in, int axis, double tau, const double *accel,
+                      double *lam, double *lam_accel)
+{
+  long d[6];
+  dims6(c, d);
+  long stride = 1;
+  for (int q = 5; q > axis; q--) stride *= d[q];
+  long n = d[axis];
+  long outer = 1;
+  for (int q = 0; q < axis; q++) outer *= d[q];
+  int periodic = (axis < 3 && c->bc == 0);
+  long nlines = outer * stride;
+  long np = nspace(c);
+  double *dnu_line = (double *)calloc(nlines, sizeof(double));
+#pragma omp parallel
+  {
+    double *in = (double *)malloc(sizeof(double) * n);
+    double *lo = (double *)malloc(sizeof(double) * n);
+    double *li = (double *)malloc(sizeof(double) * n);
+#pragma omp for schedule(static)
+    for (long line = 0; line < nlines; line++) {
+      long o = line / stride, cidx = line % stride;
+      long base = o * n * stride + cidx;
+      for (long i = 0; i < n; i++) {
+        in[i] = f_in[base + i * stride];
+        lo[i] = lam[base + i * stride];
+        li[i] = 0.0;
+      }
+      double nu = line_nu(c, axis, base, tau, accel);
+      dnu_line[line] = oracle_line_vjp(in, (int)n, nu, periodic, lo, li);
+      for (long i = 0; i < n; i++) lam[base + i * stride] = li[i];
+    }
+    free(in);
+    free(lo);
+    free(li);
+  }
+  if (axis >= 3 && lam_accel) {
+    int l = axis - 3;
+    double sc = tau / dv_of(c, l);
+    /* lines of spatial cell s: outer index o = s * (lines of preceding velocity axes) + ... */
+    long per = outer / np;  /* slabs per spatial cell */
+    for (long line = 0; line < nlines; line++) {
+      long o = line / stride;
+      long s = o / per;
+      lam_accel[(long)l * np + s] += sc * dnu_line[line];
+    }
+  }
+  free(dnu_line);
+}
+
+/* Adjoint of density -> potential -> acceleration at any state:
+ * lam_f[x, v] += dv3 * lam_rho[x], lam_rho = G_ext^T D^T lam_accel. */
+void oracle_accel_vjp(const oracle_cfg *c, const double *lam_accel, double *lam_f)
+{
+  long n0 = c->n[0], n1 = c->n[1], n2 = c->n[2], np = nspace(c), nv = nvel(c);
+  double d[3] = {dx_of(c, 0), dx_of(c, 1), dx_of(c, 2)};
+  long ne = ext_size(c);
+  double *lphi = (double *)calloc(ne, sizeof(double));
+  /* D^T: a_l(i) = -(phi(i+e_l) - phi(i-e_l)) / (2 d_l) */
+  for (long i0 = 0; i0 < n0; i0++)
+    for (long i1 = 0; i1 < n1; i1++)
+      for (long i2 = 0; i2 < n2; i2++) {
+        long s = (i0 * n1 + i1) * n2 + i2;
+        double g0 = lam_accel[s] / (2.0 * d[0]);
+        double g1 = lam_accel[np + s] / (2.0 * d[1]);
+        double g2 = lam_accel[2 * np + s] / (2.0 * d[2]);
+        lphi[ext_index(c, i0 + 1, i1, i2)] -= g0;
+        lphi[ext_index(c, i0 - 1, i1, i2)] += g0;
+        lphi[ext_index(c, i0, i1 + 1, i2)] -= g1;
+        lphi[ext_index(c, i0, i1 - 1, i2)] += g1;
+        lphi[ext_index(c, i0, i1, i2 + 1)] -= g2;
+        lphi[ext_index(c, i0, i1, i2 - 1)] += g2;
+      }
+  double *lrho = (double *)calloc(np, sizeof(double));
+  if (c->bc == 0) {
+    /* ghosts are periodic images: fold, then apply the symmetric operator */
+    double *fold = (double *)calloc(np, sizeof(double));
+    for (long t0 = -1; t0 <= n0; t0++)
+      for (long t1 = -1; t1 <= n1; t1++)
+        for (long t2 = -1; t2 <= n2; t2++) {
+          long w0 = (t0 + n0) % n0, w1 = (t1 + n1) % n1, w2 = (t2 + n2) % n2;
+          fold[(w0 * n1 + w1) * n2 + w2] += lphi[ext_index(c, t0, t1, t2)];
+        }
+    double *tmp = (double *)malloc(sizeof(double) * ne);
+    potential_periodic(c, fold, tmp);
+    for (long i0 = 0; i0 < n0; i0++)
+      for (long i1 = 0; i1 < n1; i1++)
+        for (long i2 = 0; i2 < n2; i2++) lrho[(i0 * n1 + i1) * n2 + i2] = tmp[ext_index(c, i0, i1, i2)];
+    free(fold);
+    free(tmp);
+  } else {
+    /* lam_rho(i) = sum over targets t in -1..N of K(t - i) lam_phi(t) */
+    for (long i0 = 0; i0 < n0; i0++)
+      for (long i1 = 0; i1 < n1; i1++)
+        for (long i2 = 0; i2 < n2; i2++) {
+          double acc = 0.0;
+          for (long t0 = -1; t0 <= n0; t0++)
+            for (long t1 = -1; t1 <= n1; t1++)
+              for (long t2 = -1; t2 <= n2; t2++) {
+                double g = lphi[ext_index(c, t0, t1, t2)];
+                if (g != 0.0) acc += green_isolated(c, t0 - i0, t1 - i1, t2 - i2) * g;
+              }
+          lrho[(i0 * n1 + i1) * n2 + i2] = acc;
+        }
+  }
+  double dv3 = dv_of(c, 0) * dv_of(c, 1) * dv_of(c, 2);
+  for (long s = 0; s < np; s++)
+    for (long j = 0; j < nv; j++) lam_f[s * nv + j] += dv3 * lrho[s];
+  free(lphi);
+  free(lrho);
+}
+
+/* L = -U(f_N) after nsteps steps of Eq. (17) from f0 with fixed dt; writes
+ * dL/df0 into grad (layout of f) and returns L. Keeps every intermediate
+ * state, so it is meant for small grids. */
+double oracle_grad(const oracle_cfg *c, const double *f0, int nsteps, double dt, double *grad)
+{
+  long np = nspace(c), nv = nvel(c), nc = np * nv;
+  const int axes[10] = {3, 4, 5, 2, 1, 0, -1, 3, 4, 5};
+  /* states[n][k] = input of the k-th sweep of step n (k = 0..8) */
+  double **st = (double **)malloc(sizeof(double *) * (size_t)nsteps * 9);
+  double **acc = (double **)malloc(sizeof(double *) * (size_t)(nsteps + 1));
+  double *f = (double *)malloc(sizeof(double) * nc);
+  memcpy(f, f0, sizeof(double) * nc);
+  acc[0] = (double *)malloc(sizeof(double) * 3 * np);
+  oracle_accel(c, f, acc[0]);
+  for (int n = 0; n < nsteps; n++) {
+    int k = 0;
+    for (int q = 0; q < 10; q++) {
+      if (axes[q] < 0) {
+        acc[n + 1] = (double *)malloc(sizeof(double) * 3 * np);
+        oracle_accel(c, f, acc[n + 1]);
+        continue;
+      }
+      st[n * 9 + k] = (double *)malloc(sizeof(double) * nc);
+      memcpy(st[n * 9 + k], f, sizeof(double) * nc);
+      k++;
+      double tau = axes[q] >= 3 ? 0.5 * dt : dt;
+      oracle_sweep(c, f, axes[q], tau, q < 6 ? acc[n] : acc[n + 1]);
+    }
+  }
+  /* loss and seed */
+  double *rho = (double *)malloc(sizeof(double) * np);
+  double *phi = (double *)malloc(sizeof(double) * ext_size(c));
+  oracle_density(c, f, rho);
+  oracle_potential(c, rho, phi);
+  double dx3 = dx_of(c, 0) * dx_of(c, 1) * dx_of(c, 2);
+  double dv3 = dv_of(c, 0) * dv_of(c, 1) * dv_of(c, 2);
+  double U = 0.0;
+  for (long i0 = 0; i0 < c->n[0]; i0++)
+    for (long i1 = 0; i1 < c->n[1]; i1++)
+      for (long i2 = 0; i2 < c->n[2]; i2++) {
+        long s = (i0 * c->n[1] + i1) * c->n[2] + i2;
+        U += 0.5 * rho[s] * phi[ext_index(c, i0, i1, i2)] * dx3;
+        for (long j = 0; j < nv; j++) grad[s * nv + j] = -dx3 * dv3 * phi[ext_index(c, i0, i1, i2)];
+      }
+  double *lam_pending = (double *)calloc(3 * np, sizeof(double));
+  double *lam_a = (double *)calloc(3 * np, sizeof(double));
+  for (int n = nsteps - 1; n >= 0; n--) {
+    /* second half kick of step n (acceleration a_{n+1}) */
+    memcpy(lam_a, lam_pending, sizeof(double) * 3 * np);
+    for (int k = 8; k >= 6; k--) oracle_sweep_vjp(c, st[n * 9 + k], axes[k + 1], 0.5 * dt, acc[n + 1], grad, lam_a);
+    /* a_{n+1} = A(state after the drift) */
+    oracle_accel_vjp(c, lam_a, grad);
+    /* drift */
+    for (int k = 5; k >= 3; k--) oracle_sweep_vjp(c, st[n * 9 + k], axes[k], dt, NULL, grad, NULL);
+    /* first half kick (acceleration a_n) */
+    memset(lam_pending, 0, sizeof(double) * 3 * np);
+    for (int k = 2; k >= 0; k--) oracle_sweep_vjp(c, st[n * 9 + k], axes[k], 0.5 * dt, acc[n], grad, lam_pending);
+  }
+  /* a_0 = A(f0) */
+  oracle_accel_vjp(c, lam_pending, grad);
+  for (long i = 0; i < (long)nsteps * 9; i++) free(st[i]);
+  for (int n = 0; n <= nsteps; n++) free(acc[n]);
+  free(st);
+  free(acc);
+  free(f);
+  free(rho);
+  free(phi);
+  free(lam_pending);
+  free(lam_a);
+  return -U;
+}
+
+/* L = -U of f (the loss itself, for finite differences) */
+double oracle_field_energy_loss(const oracle_cfg *c, const double *f)
+{
+  double e[4];
+  oracle_energy(c, f, e);
+  return -e[1];
+}
