@@ -158,6 +158,38 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 
+/* ---- reverse mode (gradients; an extension beyond the paper) -------------
+ *
+ * The loss is the field energy of the final state, L = -U (U of Eq. (41)),
+ * after nsteps steps of Eq. (17) with a fixed dt. The limited update is a
+ * piecewise-smooth map: the reverse mode differentiates the branch that the
+ * forward input selects (a corrector bound counts as active only when the
+ * one-sided difference is strictly beyond it; f_inf's adjoint goes to the
+ * first cell holding the line maximum).
+ *
+ * vp_sweep_adjoint: lam <- J^T lam for the single sweep T_axis(tau) taken at
+ * the forward input f_in (device, layout and type of f; lam likewise, updated
+ * in place). For a velocity axis, when lam_accel ([3][Nx][Ny][Nz] FP64, device)
+ * is not NULL, the adjoint of the stored acceleration component a_{axis-3} is
+ * added to it (the sweep moves with nu = a tau / dv).
+ *
+ * vp_accel_adjoint: lam += dv^3 G^T D^T lam_accel, the transpose of the linear
+ * map f -> density -> potential -> acceleration of Eqs. (18)-(22).
+ *
+ * vp_grad: from the current f = f0 (with the acceleration the context holds
+ * for it), runs nsteps steps forward, keeping a copy of f every ckpt_every
+ * steps and the acceleration of every step, so that the reverse sweep
+ * recomputes one segment at a time; writes dL/df0 to grad_f0_dev (device,
+ * layout and type of f, caller-owned, 16-byte aligned) and L to *loss_host.
+ * On return f holds the final state and the context its acceleration, as after
+ * vp_run(nsteps, dt). Allocates about (nsteps/ckpt_every + ckpt_every + 11)
+ * copies of f for the call and frees them before returning (VP_ENOMEM if they
+ * do not fit). Synchronises the stream. */
+int vp_sweep_adjoint(vp_ctx* ctx, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,
+                     double* lam_accel_dev);
+int vp_accel_adjoint(vp_ctx* ctx, const double* lam_accel_dev, void* lam_dev);
+int vp_grad(vp_ctx* ctx, int32_t nsteps, double dt, int32_t ckpt_every, void* grad_f0_dev, double* loss_host);
+
 /* Release everything the context owns (never f). NULL is accepted. */
 int vp_free(vp_ctx* ctx);
 

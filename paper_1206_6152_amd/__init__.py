@@ -12,13 +12,15 @@ from . import _lib
 from ._lib import (VP_BC_ISOLATED, VP_BC_PERIODIC, VP_F32, VP_F64, VPError, make_config,
                    vp_accel, vp_config_validate, vp_density, vp_drift, vp_dt, vp_energy, vp_free, vp_kick,
                    vp_get_accel, vp_init, vp_last_error, vp_potential, vp_profile_enable,
-                   vp_profile_read, vp_run, vp_set_accel, vp_step, vp_sweep)
+                   vp_profile_read, vp_run, vp_set_accel, vp_step, vp_sweep, vp_sweep_adjoint,
+                   vp_accel_adjoint, vp_grad)
 
 __all__ = ["Simulator", "VPError", "make_config", "config_of", "VP_F32", "VP_F64",
            "VP_BC_PERIODIC", "VP_BC_ISOLATED", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential",
-           "vp_energy", "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_free",
+           "vp_energy", "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint",
+           "vp_accel_adjoint", "vp_grad", "vp_free",
            "vp_last_error", "vp_config_validate"]
 
 
@@ -99,6 +101,21 @@ class Simulator:
 
     def dt(self, cfl: float) -> float:
         return vp_dt(self.ctx, cfl)
+
+    # -- reverse mode --------------------------------------------------------
+    def sweep_adjoint(self, axis: int, tau: float, f_in, lam, lam_accel=None):
+        """lam <- J^T lam for T_axis(tau) at forward input f_in (tensors like f)."""
+        vp_sweep_adjoint(self.ctx, axis, tau, f_in.data_ptr(), lam.data_ptr(),
+                         lam_accel.data_ptr() if lam_accel is not None else 0)
+
+    def accel_adjoint(self, lam_accel, lam):
+        vp_accel_adjoint(self.ctx, lam_accel.data_ptr(), lam.data_ptr())
+
+    def grad(self, nsteps: int, dt: float, ckpt_every: int = 8):
+        """(L, dL/df0) for L = -U after nsteps steps from the current f; f ends at the final state."""
+        g = self.torch.empty_like(self.f)
+        loss = vp_grad(self.ctx, nsteps, dt, ckpt_every, g.data_ptr())
+        return loss, g
 
     def profile(self, on: bool = True):
         vp_profile_enable(self.ctx, on)

@@ -32,7 +32,8 @@ ERROR_NAMES = {VP_EINVAL: "VP_EINVAL", VP_ENOMEM: "VP_ENOMEM", VP_EHIP: "VP_EHIP
 EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential", "vp_energy",
-           "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_free", "vp_last_error"]
+           "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_accel_adjoint",
+           "vp_grad", "vp_free", "vp_last_error"]
 VP_NPHASE = 8
 PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity", "kick"]
 
@@ -94,6 +95,9 @@ def lib():
             "vp_dt": [P, f64, D],
             "vp_profile_enable": [P, i32],
             "vp_profile_read": [P, D, ctypes.POINTER(ctypes.c_int64)],
+            "vp_sweep_adjoint": [P, i32, f64, P, P, P],
+            "vp_accel_adjoint": [P, P, P],
+            "vp_grad": [P, i32, f64, i32, P, D],
             "vp_free": [P],
             "vp_last_error": [],
         }
@@ -203,6 +207,21 @@ def vp_profile_read(ctx: int):
     n = (ctypes.c_int64 * VP_NPHASE)()
     check(lib().vp_profile_read(ctx, ms, n))
     return {PHASES[i]: (ms[i], n[i]) for i in range(VP_NPHASE)}
+
+
+def vp_sweep_adjoint(ctx: int, axis: int, tau: float, fin_ptr: int, lam_ptr: int, lam_accel_ptr: int = 0) -> None:
+    check(lib().vp_sweep_adjoint(ctx, int(axis), float(tau), ctypes.c_void_p(fin_ptr), ctypes.c_void_p(lam_ptr),
+                                 ctypes.c_void_p(lam_accel_ptr or None)))
+
+
+def vp_accel_adjoint(ctx: int, lam_accel_ptr: int, lam_ptr: int) -> None:
+    check(lib().vp_accel_adjoint(ctx, ctypes.c_void_p(lam_accel_ptr), ctypes.c_void_p(lam_ptr)))
+
+
+def vp_grad(ctx: int, nsteps: int, dt: float, ckpt_every: int, grad_ptr: int) -> float:
+    loss = ctypes.c_double()
+    check(lib().vp_grad(ctx, int(nsteps), float(dt), int(ckpt_every), ctypes.c_void_p(grad_ptr), ctypes.byref(loss)))
+    return loss.value
 
 
 def vp_free(ctx: int) -> None:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvp.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["sweep.hip", "gravity.hip", "vp_api.hip"]
+SOURCES = ["sweep.hip", "adjoint.hip", "gravity.hip", "vp_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

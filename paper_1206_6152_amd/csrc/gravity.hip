@@ -298,6 +298,144 @@ __global__ __launch_bounds__(RED) void accel_max_kernel(double* out, const doubl
   if (threadIdx.x == 0) out[0] = r;
 }
 
+// ---- transposes for the reverse mode ---------------------------------------
+
+// lam_phi(t), t in -1..N per axis, of a_l(i) = -(phi(i+e_l) - phi(i-e_l)) / (2 d_l):
+// lam_phi(t) = sum_l (lam_a_l(t+e_l) - lam_a_l(t-e_l)) / (2 d_l), lam_a zero outside.
+__global__ void gradient_adj_kernel(double* lphi, const double* la, Grid3 n, double d0, double d1, double d2)
+{
+  const int e0 = n.m[0] + 2, e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  const long long tot = (long long)e0 * e1 * e2;
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < tot;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int t2 = (int)(s % e2) - 1;
+    const int t1 = (int)((s / e2) % e1) - 1;
+    const int t0 = (int)(s / ((long long)e2 * e1)) - 1;
+    auto A = [&](int l, int i0, int i1, int i2) -> double {
+      if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= n.m[0] || i1 >= n.m[1] || i2 >= n.m[2]) return 0.0;
+      return la[(long long)l * np + ((long long)i0 * n.m[1] + i1) * n.m[2] + i2];
+    };
+    double v = (A(0, t0 + 1, t1, t2) - A(0, t0 - 1, t1, t2)) / (2.0 * d0);
+    v += (A(1, t0, t1 + 1, t2) - A(1, t0, t1 - 1, t2)) / (2.0 * d1);
+    v += (A(2, t0, t1, t2 + 1) - A(2, t0, t1, t2 - 1)) / (2.0 * d2);
+    lphi[s] = v;
+  }
+}
+
+// Transposed ghost fill of the periodic potential: out(i) = sum of lam_phi(t)
+// over the cells t in -1..N that are periodic images of i.
+__global__ void fold_periodic_kernel(double* out, const double* lphi, Grid3 n)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < np;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int i2 = (int)(s % n.m[2]);
+    const int i1 = (int)((s / n.m[2]) % n.m[1]);
+    const int i0 = (int)(s / ((long long)n.m[2] * n.m[1]));
+    int t[3][3], c[3];
+    const int ii[3] = {i0, i1, i2};
+    for (int l = 0; l < 3; l++) {
+      c[l] = 0;
+      t[l][c[l]++] = ii[l];
+      if (ii[l] == n.m[l] - 1) t[l][c[l]++] = -1;
+      if (ii[l] == 0) t[l][c[l]++] = n.m[l];
+    }
+    double acc = 0.0;
+    for (int a = 0; a < c[0]; a++)
+      for (int b = 0; b < c[1]; b++)
+        for (int d = 0; d < c[2]; d++)
+          acc += lphi[((long long)(t[0][a] + 1) * e1 + (t[1][b] + 1)) * e2 + (t[2][d] + 1)];
+    out[s] = acc;
+  }
+}
+
+// Place lam_phi(t), t in -1..N per axis, on the doubled grid at t mod 2N
+// (summing where two targets share a position, which happens only for N = 1).
+__global__ void load_ext_kernel(double2* data, Grid3 g, const double* lphi, Grid3 n)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < tot;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int p2 = (int)(s % g.m[2]);
+    const int p1 = (int)((s / g.m[2]) % g.m[1]);
+    const int p0 = (int)(s / ((long long)g.m[2] * g.m[1]));
+    const int pp[3] = {p0, p1, p2};
+    int t[3][2], c[3];
+    for (int l = 0; l < 3; l++) {
+      c[l] = 0;
+      if (pp[l] <= n.m[l]) t[l][c[l]++] = pp[l];
+      if (pp[l] == g.m[l] - 1) t[l][c[l]++] = -1;
+    }
+    double acc = 0.0;
+    for (int a = 0; a < c[0]; a++)
+      for (int b = 0; b < c[1]; b++)
+        for (int d = 0; d < c[2]; d++)
+          acc += lphi[((long long)(t[0][a] + 1) * e1 + (t[1][b] + 1)) * e2 + (t[2][d] + 1)];
+    data[s] = make_double2(acc, 0.0);
+  }
+}
+
+// out(i) = scale * Re data(i) for the cells i of the n-grid inside the g-grid
+__global__ void extract_interior_kernel(double* out, const double2* data, Grid3 g, Grid3 n, double scale)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < np;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int i2 = (int)(s % n.m[2]);
+    const int i1 = (int)((s / n.m[2]) % n.m[1]);
+    const int i0 = (int)(s / ((long long)n.m[2] * n.m[1]));
+    out[s] = data[((long long)i0 * g.m[1] + i1) * g.m[2] + i2].x * scale;
+  }
+}
+
+// lam[s, j] += coef * x[s] (broadcast over the velocity block)
+template <typename T>
+__global__ void broadcast_add_kernel(T* lam, const double* x, long long np, long long nv3, double coef)
+{
+  const long long tot = np * nv3;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x)
+    lam[e] = (T)((double)lam[e] + coef * x[e / nv3]);
+}
+
+// lam[s, j] = coef * phi(interior cell s)
+template <typename T>
+__global__ void seed_kernel(T* lam, const double* phi, Grid3 n, long long nv3, double coef)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  const long long tot = np * nv3;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long s = e / nv3;
+    const long long i2 = s % n.m[2];
+    const long long i1 = (s / n.m[2]) % n.m[1];
+    const long long i0 = s / ((long long)n.m[2] * n.m[1]);
+    lam[e] = (T)(coef * phi[((i0 + 1) * e1 + (i1 + 1)) * e2 + (i2 + 1)]);
+  }
+}
+
+// out[0] = 1/2 sum rho phi dx3 (the potential energy, fixed order)
+__global__ __launch_bounds__(RED) void potential_energy_kernel(double* out, const double* rho, const double* phi,
+                                                               Grid3 n, double dx3)
+{
+  __shared__ double sh[RED];
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  double u = 0.0;
+  for (long long s = threadIdx.x; s < np; s += RED) {
+    const long long i2 = s % n.m[2];
+    const long long i1 = (s / n.m[2]) % n.m[1];
+    const long long i0 = s / ((long long)n.m[2] * n.m[1]);
+    u += rho[s] * phi[((i0 + 1) * e1 + (i1 + 1)) * e2 + (i2 + 1)];
+  }
+  const double us = block_sum(u, sh);
+  if (threadIdx.x == 0) out[0] = 0.5 * us * dx3;
+}
+
 unsigned grid_for(long long n, int block)
 {
   long long b = (n + block - 1) / block;
@@ -307,6 +445,68 @@ unsigned grid_for(long long n, int block)
 }
 
 }  // namespace
+
+hipError_t launch_gradient_adj(double* lphi, const double* la, Grid3 n, double d0, double d1, double d2,
+                               hipStream_t s)
+{
+  const long long tot = (long long)(n.m[0] + 2) * (n.m[1] + 2) * (n.m[2] + 2);
+  hipLaunchKernelGGL(gradient_adj_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, lphi, la, n, d0, d1, d2);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_periodic(double* out, const double* lphi, Grid3 n, hipStream_t s)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  hipLaunchKernelGGL(fold_periodic_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, out, lphi, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_ext(double2* data, Grid3 g, const double* lphi, Grid3 n, hipStream_t s)
+{
+  const long long tot = (long long)g.m[0] * g.m[1] * g.m[2];
+  hipLaunchKernelGGL(load_ext_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, s, data, g, lphi, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_interior(double* out, const double2* data, Grid3 g, Grid3 n, double scale, hipStream_t s)
+{
+  const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
+  hipLaunchKernelGGL(extract_interior_kernel, dim3(grid_for(np, 256)), dim3(256), 0, s, out, data, g, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_broadcast_add(void* lam, int dtype, const double* x, long long np, long long nv3, double coef,
+                                hipStream_t s)
+{
+  const long long tot = np * nv3;
+  if (dtype == 0)
+    hipLaunchKernelGGL(broadcast_add_kernel<float>, dim3(grid_for(tot, 256)), dim3(256), 0, s, (float*)lam, x, np,
+                       nv3, coef);
+  else
+    hipLaunchKernelGGL(broadcast_add_kernel<double>, dim3(grid_for(tot, 256)), dim3(256), 0, s, (double*)lam, x,
+                       np, nv3, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(void* lam, int dtype, const double* phi_ext, Grid3 n, long long nv3, double coef,
+                       hipStream_t s)
+{
+  const long long tot = (long long)n.m[0] * n.m[1] * n.m[2] * nv3;
+  if (dtype == 0)
+    hipLaunchKernelGGL(seed_kernel<float>, dim3(grid_for(tot, 256)), dim3(256), 0, s, (float*)lam, phi_ext, n, nv3,
+                       coef);
+  else
+    hipLaunchKernelGGL(seed_kernel<double>, dim3(grid_for(tot, 256)), dim3(256), 0, s, (double*)lam, phi_ext, n,
+                       nv3, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_potential_energy(double* out, const double* rho, const double* phi_ext, Grid3 n, double dx3,
+                                   hipStream_t s)
+{
+  hipLaunchKernelGGL(potential_energy_kernel, dim3(1), dim3(RED), 0, s, out, rho, phi_ext, n, dx3);
+  return hipGetLastError();
+}
 
 hipError_t launch_density(const void* f, int dtype, double* rho, long long np, long long nv3, double dv3,
                           hipStream_t s)

@@ -63,6 +63,11 @@ struct vp_ctx {
   double* part = nullptr;     // 2 * np
   double* red = nullptr;      // 8 doubles on the device
   double* host = nullptr;     // 8 pinned doubles
+  // reverse-mode work fields (allocated on first use)
+  double* lphi = nullptr;     // (N+2)^3
+  double* radj = nullptr;     // np
+  double* dnu = nullptr;      // one value per line of a sweep
+  long long dnu_len = 0;
   // phase timing (vp_profile_*): pending event pairs per phase
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;
@@ -118,6 +123,9 @@ void release(vp_ctx* c)
   for (auto& t : c->tw) hipFree(t);
   hipFree(c->part);
   hipFree(c->red);
+  hipFree(c->lphi);
+  hipFree(c->radj);
+  hipFree(c->dnu);
   if (c->host) hipHostFree(c->host);
   for (auto& p : c->ev_pending) {
     hipEventDestroy(p.second.first);
@@ -189,13 +197,11 @@ int drain_events(vp_ctx* c)
   return VP_OK;
 }
 
-// density -> rho, Poisson -> phi (with ghosts)
-int potential_into(vp_ctx* c, double* phi_out)
+// potential (with ghosts) of the density held in rho_in
+int poisson_from(vp_ctx* c, const double* rho_in, double* phi_out)
 {
   const bool iso = c->cfg.bc == VP_BC_ISOLATED;
-  LAUNCH(c, vp::launch_density(c->f, c->cfg.dtype, c->rho, c->np, c->nv3,
-                               c->dv[0] * c->dv[1] * c->dv[2], c->stream));
-  LAUNCH(c, vp::launch_load_rho(c->work, c->wg, c->rho, c->ng, c->stream));
+  LAUNCH(c, vp::launch_load_rho(c->work, c->wg, rho_in, c->ng, c->stream));
   for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, -1, c->tw[ax], c->stream));
   if (iso)
     LAUNCH(c, vp::launch_mul_spectrum(c->work, c->kspec, prod3(c->wg.m), c->stream));
@@ -204,6 +210,14 @@ int potential_into(vp_ctx* c, double* phi_out)
   for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, +1, c->tw[ax], c->stream));
   LAUNCH(c, vp::launch_extract_phi(phi_out, c->ng, c->work, c->wg, 1.0 / (double)prod3(c->wg.m), c->stream));
   return VP_OK;
+}
+
+// density -> rho, Poisson -> phi (with ghosts)
+int potential_into(vp_ctx* c, double* phi_out)
+{
+  LAUNCH(c, vp::launch_density(c->f, c->cfg.dtype, c->rho, c->np, c->nv3,
+                               c->dv[0] * c->dv[1] * c->dv[2], c->stream));
+  return poisson_from(c, c->rho, phi_out);
 }
 
 int compute_accel(vp_ctx* c)
@@ -215,7 +229,7 @@ int compute_accel(vp_ctx* c)
   return VP_OK;
 }
 
-int sweep(vp_ctx* c, int axis, double tau)
+vp::SweepArgs sweep_args(vp_ctx* c, int axis, double tau)
 {
   const auto& k = c->cfg;
   long long d[6] = {k.n[0], k.n[1], k.n[2], k.nv[0], k.nv[1], k.nv[2]};
@@ -248,8 +262,64 @@ int sweep(vp_ctx* c, int axis, double tau)
     a.dv = c->dv[axis];
     a.sp_div = 1;
   }
+  return a;
+}
+
+int sweep(vp_ctx* c, int axis, double tau)
+{
+  const vp::SweepArgs a = sweep_args(c, axis, tau);
   PhaseScope scope(c, axis);
-  LAUNCH(c, vp::launch_sweep(a, k.dtype, c->stream));
+  LAUNCH(c, vp::launch_sweep(a, c->cfg.dtype, c->stream));
+  return VP_OK;
+}
+
+// lam <- J^T lam of T_axis(tau) at forward input fin; velocity axes add the
+// acceleration adjoint to lam_a (if not null).
+int sweep_adjoint(vp_ctx* c, int axis, double tau, const void* fin, void* lam, double* lam_a)
+{
+  const vp::SweepArgs a = sweep_args(c, axis, tau);
+  const bool want = axis >= 3 && lam_a;
+  if (want && a.nlines > c->dnu_len) {
+    hipFree(c->dnu);
+    c->dnu = nullptr;
+    c->dnu_len = 0;
+    int r = dalloc(&c->dnu, sizeof(double) * a.nlines, "line adjoints");
+    if (r) return r;
+    c->dnu_len = a.nlines;
+  }
+  LAUNCH(c, vp::launch_sweep_adjoint(a, c->cfg.dtype, fin, lam, want ? c->dnu : nullptr, c->stream));
+  if (want) {
+    const int l = axis - 3;
+    LAUNCH(c, vp::launch_reduce_lines(lam_a + (long long)l * c->np, c->dnu, c->np, a.nlines / c->np,
+                                      tau / c->dv[l], c->stream));
+  }
+  return VP_OK;
+}
+
+// lam += dv^3 G^T D^T lam_a: transpose of density -> potential -> acceleration
+int accel_adjoint(vp_ctx* c, const double* lam_a, void* lam)
+{
+  const long long ext = (long long)(c->cfg.n[0] + 2) * (c->cfg.n[1] + 2) * (c->cfg.n[2] + 2);
+  int r;
+  if (!c->lphi && (r = dalloc(&c->lphi, sizeof(double) * ext, "potential adjoint"))) return r;
+  if (!c->radj && (r = dalloc(&c->radj, sizeof(double) * c->np, "density adjoint"))) return r;
+  LAUNCH(c, vp::launch_gradient_adj(c->lphi, lam_a, c->ng, c->dx[0], c->dx[1], c->dx[2], c->stream));
+  if (c->cfg.bc == VP_BC_ISOLATED) {
+    LAUNCH(c, vp::launch_load_ext(c->work, c->wg, c->lphi, c->ng, c->stream));
+    for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, -1, c->tw[ax], c->stream));
+    LAUNCH(c, vp::launch_mul_spectrum(c->work, c->kspec, prod3(c->wg.m), c->stream));
+    for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, +1, c->tw[ax], c->stream));
+    LAUNCH(c, vp::launch_extract_interior(c->radj, c->work, c->wg, c->ng, 1.0 / (double)prod3(c->wg.m), c->stream));
+  } else {
+    LAUNCH(c, vp::launch_fold_periodic(c->radj, c->lphi, c->ng, c->stream));
+    LAUNCH(c, vp::launch_load_rho(c->work, c->wg, c->radj, c->ng, c->stream));
+    for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, -1, c->tw[ax], c->stream));
+    LAUNCH(c, vp::launch_green_periodic(c->work, c->wg, c->cfg.G, c->dx[0], c->dx[1], c->dx[2], c->stream));
+    for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, +1, c->tw[ax], c->stream));
+    LAUNCH(c, vp::launch_extract_interior(c->radj, c->work, c->wg, c->ng, 1.0 / (double)prod3(c->wg.m), c->stream));
+  }
+  LAUNCH(c, vp::launch_broadcast_add(lam, c->cfg.dtype, c->radj, c->np, c->nv3, c->dv[0] * c->dv[1] * c->dv[2],
+                                     c->stream));
   return VP_OK;
 }
 
@@ -543,6 +613,160 @@ int vp_dt(vp_ctx* c, double cfl, double* dt_host)
   const double dtv = amax > 0 ? 1.0 / amax : INFINITY;
   *dt_host = cfl * std::fmin(dtp, dtv);
   return VP_OK;
+}
+
+int vp_sweep_adjoint(vp_ctx* c, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,
+                     double* lam_accel_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (axis < 0 || axis > 5) return fail(VP_EINVAL, "axis must be 0..5");
+  if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
+  if (!f_in_dev || !lam_dev) return fail(VP_EINVAL, "null pointer");
+  return sweep_adjoint(c, axis, tau, f_in_dev, lam_dev, lam_accel_dev);
+}
+
+int vp_accel_adjoint(vp_ctx* c, const double* lam_accel_dev, void* lam_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!lam_accel_dev || !lam_dev) return fail(VP_EINVAL, "null pointer");
+  return accel_adjoint(c, lam_accel_dev, lam_dev);
+}
+
+namespace {
+
+struct GradWork {
+  vp_ctx* c;
+  std::vector<void*> bufs;
+  std::vector<double*> dbufs;
+  ~GradWork()
+  {
+    for (void* p : bufs) hipFree(p);
+    for (double* p : dbufs) hipFree(p);
+  }
+  int f(void** p, size_t bytes)
+  {
+    int r = dalloc(p, bytes, "gradient work");
+    if (!r) bufs.push_back(*p);
+    return r;
+  }
+  int d(double** p, size_t bytes)
+  {
+    int r = dalloc(p, bytes, "gradient work");
+    if (!r) dbufs.push_back(*p);
+    return r;
+  }
+};
+
+int copy_f(vp_ctx* c, void* dst, const void* src, size_t bytes)
+{
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return VP_OK;
+}
+
+// Reverse mode of nsteps steps of Eq. (17) with checkpoints; see vp.h.
+int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
+{
+  const size_t fb = (size_t)c->np * (size_t)c->nv3 * (c->cfg.dtype == VP_F32 ? 4 : 8);
+  const size_t ab = sizeof(double) * 3 * (size_t)c->np;
+  const int nck = (nsteps + k - 1) / k;
+  void* user_f = c->f;
+  GradWork w{c};
+  std::vector<void*> ck(nck), stepb(k), sb(9);
+  void *W = nullptr, *fin = nullptr;
+  double *ahist = nullptr, *lam_a = nullptr, *lam_p = nullptr;
+  int r;
+  for (int i = 0; i < nck; i++)
+    if ((r = w.f(&ck[i], fb))) return r;
+  for (int i = 0; i < k; i++)
+    if ((r = w.f(&stepb[i], fb))) return r;
+  for (int i = 0; i < 9; i++)
+    if ((r = w.f(&sb[i], fb))) return r;
+  if ((r = w.f(&W, fb)) || (r = w.f(&fin, fb))) return r;
+  if ((r = w.d(&ahist, ab * (size_t)(nsteps + 1))) || (r = w.d(&lam_a, ab)) || (r = w.d(&lam_p, ab))) return r;
+  auto A = [&](int n) { return ahist + (size_t)n * 3 * c->np; };
+  auto set_accel = [&](int n) { return copy_f(c, c->accel, A(n), ab); };
+
+  // forward pass from f0, keeping checkpoints and every step's acceleration
+  if ((r = copy_f(c, A(0), c->accel, ab))) return r;
+  const double h = 0.5 * dt;
+  for (int n = 0; n < nsteps; n++) {
+    if (n % k == 0 && (r = copy_f(c, ck[n / k], user_f, fb))) return r;
+    if ((r = kick(c, h)) || (r = drift(c, dt)) || (r = compute_accel(c)) || (r = kick(c, h))) return r;
+    if ((r = copy_f(c, A(n + 1), c->accel, ab))) return r;
+  }
+  if ((r = copy_f(c, fin, user_f, fb))) return r;
+  // loss = -U of the final state, seed lam = dL/df = -dx^3 dv^3 phi(x)
+  if ((r = potential_into(c, c->phi))) return r;
+  const double dx3 = c->dx[0] * c->dx[1] * c->dx[2], dv3 = c->dv[0] * c->dv[1] * c->dv[2];
+  LAUNCH(c, vp::launch_potential_energy(c->red, c->rho, c->phi, c->ng, dx3, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->host, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  LAUNCH(c, vp::launch_seed(lam, c->cfg.dtype, c->phi, c->ng, c->nv3, -dx3 * dv3, c->stream));
+  HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
+
+  static const int axes[9] = {3, 4, 5, 2, 1, 0, 3, 4, 5};
+  c->f = W;
+  for (int seg = nck - 1; seg >= 0 && r == VP_OK; seg--) {
+    const int s0 = seg * k, s1 = (s0 + k < nsteps) ? s0 + k : nsteps;
+    if ((r = copy_f(c, W, ck[seg], fb))) break;
+    for (int n = s0; n < s1 && r == VP_OK; n++) {
+      if ((r = copy_f(c, stepb[n - s0], W, fb))) break;
+      if (n + 1 < s1) {
+        if ((r = set_accel(n))) break;
+        if ((r = kick(c, h)) || (r = drift(c, dt)) || (r = compute_accel(c)) || (r = kick(c, h))) break;
+      }
+    }
+    for (int n = s1 - 1; n >= s0 && r == VP_OK; n--) {
+      // inputs of the nine sweeps of step n
+      if ((r = copy_f(c, W, stepb[n - s0], fb)) || (r = set_accel(n))) break;
+      for (int q = 0; q < 9 && r == VP_OK; q++) {
+        if (q == 6 && (r = set_accel(n + 1))) break;
+        if ((r = copy_f(c, sb[q], W, fb))) break;
+        r = sweep(c, axes[q], q >= 3 && q < 6 ? dt : h);
+      }
+      if (r) break;
+      // second half kick (acceleration a_{n+1}), then a_{n+1} = A(state after the drift)
+      if ((r = copy_f(c, lam_a, lam_p, ab))) break;
+      for (int q = 8; q >= 6 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, sb[q], lam, lam_a);
+      if (r || (r = accel_adjoint(c, lam_a, lam))) break;
+      for (int q = 5; q >= 3 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], dt, sb[q], lam, nullptr);
+      if (r) break;
+      if ((r = set_accel(n))) break;
+      HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
+      for (int q = 2; q >= 0 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, sb[q], lam, lam_p);
+    }
+  }
+  c->f = user_f;
+  if (r) return r;
+  // a_0 = A(f0)
+  if ((r = accel_adjoint(c, lam_p, lam))) return r;
+  if ((r = copy_f(c, user_f, fin, fb)) || (r = set_accel(nsteps))) return r;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *loss = -c->host[0];
+  return VP_OK;
+}
+
+}  // namespace
+
+int vp_grad(vp_ctx* c, int32_t nsteps, double dt, int32_t ckpt_every, void* grad_f0_dev, double* loss_host)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (nsteps < 0) return fail(VP_EINVAL, "nsteps must be >= 0");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(VP_EINVAL, "dt must be finite and > 0");
+  if (ckpt_every < 1) return fail(VP_EINVAL, "ckpt_every must be >= 1");
+  if (!grad_f0_dev || !loss_host) return fail(VP_EINVAL, "null pointer");
+  if (reinterpret_cast<uintptr_t>(grad_f0_dev) % 16 != 0) return fail(VP_EINVAL, "gradient must be 16-byte aligned");
+  const bool prof = c->profiling;
+  c->profiling = false;
+  r = grad_impl(c, nsteps, dt, ckpt_every, grad_f0_dev, loss_host);
+  c->profiling = prof;
+  if (r) hipStreamSynchronize(c->stream);
+  return r;
 }
 
 int vp_profile_enable(vp_ctx* c, int32_t on)

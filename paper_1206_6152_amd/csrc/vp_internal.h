@@ -105,4 +105,26 @@ hipError_t launch_energy_final(double* out, const double* part, const double* rh
 hipError_t launch_accel_max(double* out, const double* accel, long long np, double i0, double i1,
                             double i2, hipStream_t s);
 
+// ---- reverse mode -------------------------------------------------------------
+
+// lam <- J^T lam for the sweep described by a at forward input fin; the
+// per-line d<lam, out>/d nu goes to dnu[line] when dnu is not null.
+hipError_t launch_sweep_adjoint(const SweepArgs& a, int dtype, const void* fin, void* lam, double* dnu,
+                                hipStream_t s);
+// lam_a[s] += scale * sum_{i < per} dnu[s*per + i], s < np
+hipError_t launch_reduce_lines(double* lam_a, const double* dnu, long long np, long long per, double scale,
+                               hipStream_t s);
+hipError_t launch_gradient_adj(double* lphi_ext, const double* lam_a, Grid3 n, double d0, double d1, double d2,
+                               hipStream_t s);
+hipError_t launch_fold_periodic(double* out, const double* lphi_ext, Grid3 n, hipStream_t s);
+hipError_t launch_load_ext(double2* data, Grid3 g, const double* lphi_ext, Grid3 n, hipStream_t s);
+hipError_t launch_extract_interior(double* out, const double2* data, Grid3 g, Grid3 n, double scale,
+                                   hipStream_t s);
+hipError_t launch_broadcast_add(void* lam, int dtype, const double* x, long long np, long long nv3, double coef,
+                                hipStream_t s);
+hipError_t launch_seed(void* lam, int dtype, const double* phi_ext, Grid3 n, long long nv3, double coef,
+                       hipStream_t s);
+hipError_t launch_potential_energy(double* out, const double* rho, const double* phi_ext, Grid3 n, double dx3,
+                                   hipStream_t s);
+
 }  // namespace vp

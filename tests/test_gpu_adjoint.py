@@ -1,0 +1,177 @@
+"""GPU parity of the reverse mode through the C ABI against the oracle's reverse
+mode (single sweeps with their acceleration adjoints, the transposed gravity
+map, short multi-step gradients), and of the adjoint workload (16^3 x 24^3,
+40 steps, checkpoints every 8) against central finite differences of the GPU
+forward map in FP64 and against the FP64 gradient for the FP32 path."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import oracle_grid, rel_l1, small_workload, structured_f
+from paper_1206_6152_amd import VP_BC_ISOLATED, VP_BC_PERIODIC, VP_F32, VP_F64, Simulator, config_of, inputs
+
+pytestmark = pytest.mark.gpu
+
+NP = {VP_F64: np.float64, VP_F32: np.float32}
+
+
+def _t():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _dev(x, dtype=None):
+    torch = _t()
+    return torch.from_numpy(np.ascontiguousarray(x if dtype is None else x.astype(dtype))).to("cuda:0")
+
+
+@pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+@pytest.mark.parametrize("axis", [0, 1, 2, 3, 4, 5])
+def test_sweep_adjoint_matches_oracle(axis, bc, dtype):
+    print("case", axis, bc, dtype, flush=True)
+    w = small_workload(bc, n=(4, 6, 8), nv=(12, 8, 6))
+    rng = np.random.default_rng(40 + axis)
+    f_in = (structured_f(w.shape, 50 + axis) + 0.01 + 1e-3 * rng.uniform(0, 1, w.shape))
+    f_in = f_in.astype(NP[dtype]).astype(np.float64)
+    lam = rng.standard_normal(w.shape).astype(NP[dtype]).astype(np.float64)
+    tau = 0.31 if axis >= 3 else -0.9 * w.dx(axis) / max(abs(w.vmin[axis]), abs(w.vmax[axis]))
+    a = rng.uniform(-1, 1, (3,) + w.n) * 1.3 * np.array([w.dv(l) for l in range(3)]).reshape(3, 1, 1, 1) / abs(tau)
+    g = oracle_grid(w)
+    ref_lam, ref_la = oracle.sweep_vjp(g, f_in, axis, tau, lam, a)
+    torch = _t()
+    f = _dev(f_in, NP[dtype])
+    sim = Simulator(config_of(w, dtype), f)
+    sim.set_accel(_dev(a))
+    lam_d = _dev(lam, NP[dtype])
+    la_d = torch.zeros((3,) + w.n, dtype=torch.float64, device="cuda:0")
+    sim.sweep_adjoint(axis, tau, _dev(f_in, NP[dtype]), lam_d, la_d)
+    out = lam_d.cpu().numpy().astype(np.float64)
+    la = la_d.cpu().numpy()
+    sim.close()
+    tol = 1e-12 if dtype == VP_F64 else 2e-5
+    assert rel_l1(out, ref_lam) <= tol
+    if axis >= 3:
+        assert rel_l1(la, ref_la) <= (1e-11 if dtype == VP_F64 else 1e-4)
+
+
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+def test_accel_adjoint_matches_oracle(bc):
+    w = small_workload(bc, n=(4, 6, 8), nv=(4, 3, 2))
+    rng = np.random.default_rng(3)
+    la = rng.standard_normal((3,) + w.n)
+    ref = oracle.accel_vjp(oracle_grid(w), la)
+    torch = _t()
+    f = _dev(np.ones(w.shape))
+    sim = Simulator(config_of(w, VP_F64), f)
+    lam = torch.zeros(w.shape, dtype=torch.float64, device="cuda:0")
+    sim.accel_adjoint(_dev(la), lam)
+    out = lam.cpu().numpy()
+    sim.close()
+    assert rel_l1(out, ref) <= 1e-12
+
+
+def _tiny(bc):
+    if bc == VP_BC_PERIODIC:
+        s = inputs.jeans_sigma(0.5, 2 * np.pi)
+        w = inputs.Workload(name="t", n=(4, 2, 2), nv=(8, 4, 4), L=(1.0, 0.5, 0.5), vmin=(-4 * s,) * 3,
+                            vmax=(4 * s,) * 3, G=1.0, bc=0, dt=0.04, steps=5, params=dict(sigma=s, amp=0.1))
+        f0 = inputs.initial_f(w)
+        f0 *= 1 + 0.05 * np.random.default_rng(4).standard_normal(w.n).reshape(w.n + (1, 1, 1))
+    else:
+        w = inputs.Workload(name="t", n=(4, 4, 4), nv=(6, 6, 6), L=(4.0, 4.0, 4.0), vmin=(-2.0,) * 3,
+                            vmax=(2.0,) * 3, G=1.0, bc=1, dt=0.2, steps=3, params=dict(sigma=0.6))
+        X = np.meshgrid(*[w.xc(l) for l in range(3)], indexing="ij")
+        dens = np.exp(-(X[0] ** 2 + X[1] ** 2 + X[2] ** 2) / 2.0)
+        f0 = dens.reshape(w.n + (1, 1, 1)) * inputs.maxwellian(w, 0.6).reshape((1, 1, 1) + w.nv)
+    # symmetric data has exactly tied line maxima; rounding of either side then
+    # decides which cell receives f_inf's adjoint (both are valid), so break
+    # the ties well above rounding
+    f0 = f0 * (1 + 1e-4 * np.random.default_rng(11).uniform(0, 1, f0.shape))
+    return w, f0
+
+
+@pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+@pytest.mark.parametrize("ckpt", [1, 2, 8])
+def test_grad_matches_oracle(bc, dtype, ckpt):
+    w, f0 = _tiny(bc)
+    f0 = f0.astype(NP[dtype]).astype(np.float64)
+    L_ref, g_ref = oracle.grad(oracle_grid(w), f0, w.steps, w.dt)
+    f = _dev(f0, NP[dtype])
+    sim = Simulator(config_of(w, dtype), f)
+    L, g = sim.grad(w.steps, w.dt, ckpt)
+    out = g.cpu().numpy().astype(np.float64)
+    fin = f.cpu().numpy().astype(np.float64)
+    sim.close()
+    run = oracle.Run(oracle_grid(w), f0)
+    for _ in range(w.steps):
+        run.step(w.dt)
+    print("grad", bc, dtype, ckpt, "L", L, L_ref, "rel L1", rel_l1(out, g_ref), flush=True)
+    if dtype == VP_F64:
+        assert L == pytest.approx(L_ref, rel=1e-12)
+        assert rel_l1(out, g_ref) <= 1e-10
+        assert rel_l1(fin, run.f) <= 1e-12      # f ends at the final state
+    else:
+        assert L == pytest.approx(L_ref, rel=1e-5)
+        assert rel_l1(out, g_ref) <= 1e-3
+        assert rel_l1(fin, run.f) <= 1e-5
+
+
+def test_adjoint_workload_against_finite_differences():
+    # the 16^3 x 24^3 adjoint workload: Jeans sigma, delta ~ N(0, 1e-3^2) per
+    # spatial cell, 40 steps, checkpoints every 8; FD of the GPU FP64 forward
+    torch = _t()
+    from paper_1206_6152_amd.autograd import field_energy, initial_f
+    w = inputs.jeans_adjoint_16_24()
+    dens, m = inputs.separable_factors(w)
+    delta = _dev(dens - 1.0).requires_grad_(True)
+    m_v = _dev(m)
+    L64 = field_energy(delta, m_v, w, VP_F64, w.steps, w.dt, 8)
+    L64.backward()
+    g64 = delta.grad.detach().clone()
+    delta.grad = None
+    L32 = field_energy(delta, m_v, w, VP_F32, w.steps, w.dt, 8)
+    L32.backward()
+    g32 = delta.grad.detach().clone()
+    r32 = float((g32 - g64).abs().sum() / g64.abs().sum())
+    print("L64", float(L64), "L32", float(L32), "FP32 vs FP64 gradient rel L1", r32, flush=True)
+    assert r32 <= 1e-3
+
+    def loss_at(d):
+        f = initial_f(d, m_v, 1.0, torch.float64)
+        sim = Simulator(config_of(w, VP_F64), f)
+        sim.run(w.steps, w.dt)
+        e = sim.energy()
+        sim.close()
+        return -e[1]
+
+    rng = np.random.default_rng(6152)
+    dirs = [rng.standard_normal(w.n) for _ in range(8)]
+    for c in [tuple(int(rng.integers(0, n)) for n in w.n) for _ in range(8)]:
+        e = np.zeros(w.n)
+        e[c] = 1.0
+        dirs.append(e)
+    # the limited map is piecewise smooth: a central difference with a step that
+    # crosses corrector kinks departs from the derivative of the piece the
+    # state is in, so the check takes the best of three steps, and measures the
+    # error on the scale |grad| |d| (a directional derivative can be small by
+    # cancellation)
+    gnorm = float(g64.norm())
+    worst, worst_1e4 = 0.0, 0.0
+    for k, d in enumerate(dirs):
+        d = _dev(d)
+        an = float((g64 * d).sum())
+        scale = gnorm * float(d.norm())
+        res = []
+        for eps in (1e-4, 1e-5, 1e-6):
+            fd = (loss_at(delta.detach() + eps * d) - loss_at(delta.detach() - eps * d)) / (2 * eps)
+            res.append(fd)
+        err = min(abs(an - fd) for fd in res) / scale
+        e4 = abs(an - res[0]) / scale
+        print("direction", k, "adjoint", an, "FD(1e-4,1e-5,1e-6)", res, "err/(|g||d|) best", err,
+              "at eps=1e-4", e4, flush=True)
+        worst, worst_1e4 = max(worst, err), max(worst_1e4, e4)
+    print("worst error on the |g||d| scale: best step", worst, "eps=1e-4", worst_1e4, flush=True)
+    assert worst <= 1e-4
