@@ -97,10 +97,20 @@ def committed_traffic(w, elem_bytes, kernel):
     return traffic.get(kernel)
 
 
+PHASE_KERNEL = {
+    "kick": "one-pass half kick (T_vx, T_vy, T_vz of each velocity block)",
+    "kick2": "one-pass pair of half kicks (two T_vz T_vy T_vx with one acceleration)",
+    "drift_yz": "one-pass T_y T_z (x-slab x velocity-chunk tiles)",
+}
+
+
 def kernel_name(phase, w, elem_bytes):
     t = "float" if elem_bytes == 4 else "double"
-    if phase == "kick":
-        return "vp::kick_block<%s, %d, %d, %d>" % (t, w.nv[0], w.nv[1], w.nv[2])
+    if phase in ("kick", "kick2"):
+        return "vp::kick_block<%s, %d, %d, %d, %d>" % (t, w.nv[0], w.nv[1], w.nv[2], 2 if phase == "kick2" else 1)
+    if phase == "drift_yz":
+        wd = {16: 64, 24: 32, 32: 32}[w.n[1]] if elem_bytes == 4 else {16: 32, 24: 16, 32: 16}[w.n[1]]
+        return "vp::drift_yz_block<%s, %d, %d, %d>" % (t, w.n[1], w.n[2], wd)
     axis = ["x", "y", "z", "vx", "vy", "vz"].index(phase)
     n = (list(w.n) + list(w.nv))[axis]
     kind = "sweep_contig" if axis == 5 else "sweep_strided"
@@ -133,7 +143,7 @@ def gpu_run(w, vp_dtype, steps, warmup):
     del f
     torch.cuda.empty_cache()
     per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in phases.items()}
-    sweep_tot = {k: phases[k][0] for k in ("x", "y", "z", "vx", "vy", "vz", "kick")}
+    sweep_tot = {k: phases[k][0] for k in ("x", "y", "z", "vx", "vy", "vz", "kick", "kick2", "drift_yz")}
     dom = max(sweep_tot, key=sweep_tot.get)
     dom_ms = per_launch[dom]
     sweep_bytes = 2.0 * s * cells          # read + write f once per launch (one sweep or one fused kick)
@@ -147,8 +157,7 @@ def gpu_run(w, vp_dtype, steps, warmup):
         ms_per_step=step_ms,
         bytes_per_elem=s,
         dominant=dom,
-        roofline=dict(bound="hbm", kernel=("one-pass half kick (vx, vy, vz sweeps)" if dom == "kick"
-                                           else "pfc sweep along %s" % dom), achieved=achieved,
+        roofline=dict(bound="hbm", kernel=PHASE_KERNEL.get(dom, "pfc sweep along %s" % dom), achieved=achieved,
                       peak=PEAK_HBM_GBPS, unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
                       traffic=traffic, traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
                       "copy-calibrated)", hip_kernel=kname, algorithmic_bytes_per_launch=sweep_bytes,

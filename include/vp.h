@@ -98,7 +98,9 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out);
  * states. dt must be finite and > 0. */
 int vp_step(vp_ctx* ctx, double dt);
 
-/* n consecutive vp_step calls with the same dt (n >= 0). */
+/* n consecutive vp_step calls with the same dt (n >= 0), with the same result
+ * bit for bit. The closing half kick of one step and the opening half kick of
+ * the next use the same acceleration; they run as one pass over f. */
 int vp_run(vp_ctx* ctx, int32_t nsteps, double dt);
 
 /* A single one-dimensional PFC advection T_axis(tau) of every line of f
@@ -113,7 +115,9 @@ int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
  * exactly the corresponding vp_sweep calls in that order (same arithmetic, same
  * result bit for bit); vp_kick runs the three velocity sweeps of a spatial
  * cell in one pass over f when that cell's velocity block fits on chip
- * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3). */
+ * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3), and vp_drift runs
+ * T_z and T_y in one pass when a (y, z) plane of a slab of velocity cells
+ * fits on chip (square 16^2, 24^2 or 32^2 planes), then T_x. */
 int vp_kick(vp_ctx* ctx, double tau);
 int vp_drift(vp_ctx* ctx, double tau);
 
@@ -153,8 +157,10 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * returns, per phase, the summed event time in milliseconds and the number of
  * launches: phases 0..5 are the sweeps along x, y, z, vx, vy, vz, phase 6 the
  * gravity solve (density, Poisson, acceleration), phase 7 the one-pass half
- * kick. Arrays have VP_NPHASE entries and are caller-owned host memory. */
-#define VP_NPHASE 8
+ * kick, phase 8 the one-pass pair of half kicks of vp_run, phase 9 the
+ * one-pass T_y T_z. Arrays have VP_NPHASE entries and are caller-owned host
+ * memory. */
+#define VP_NPHASE 10
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 

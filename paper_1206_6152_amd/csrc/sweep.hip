@@ -249,7 +249,7 @@ __device__ __forceinline__ int kick_lds_index(int e)
   return jx * S::SX + jy * S::SY + jz;
 }
 
-template <typename T, int NX, int NY, int NZ>
+template <typename T, int NX, int NY, int NZ, int REPS>
 __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_block(KickArgs a)
 {
   using S = KickShape<T, NX, NY, NZ>;
@@ -260,33 +260,18 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
   __shared__ T L[S::ELEMS];
   const int tid = threadIdx.x;
   const long long s = blockIdx.x;
-  VT* g = reinterpret_cast<VT*>(static_cast<T*>(a.f) + s * S::NV3);
-
-  {
-    VT x[PER];
-#pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const int i = tid + k * S::THREADS;
-      if (i < NVEC) x[k] = g[i];
-    }
-#pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const int i = tid + k * S::THREADS;
-      if (i < NVEC) {
-#pragma unroll
-        for (int q = 0; q < V; q++) L[kick_lds_index<T, NX, NY, NZ>(i * V + q)] = lane_of<VT, T>(x[k], q);
-      }
-    }
-  }
+  T* gs = static_cast<T*>(a.f) + s * S::NV3;
+  VT* g = reinterpret_cast<VT*>(gs);
   const double nux = a.a[0][s] * a.scale[0];
   const double nuy = a.a[1][s] * a.scale[1];
   const double nuz = a.a[2][s] * a.scale[2];
-  __syncthreads();
-  if (tid < S::L0) {  // vx lines: (jy, jz)
+  // first vx sweep, lane (jy, jz): the line comes straight from HBM (a row of
+  // a wave is 64 consecutive values) and goes to LDS after the update
+  if (tid < S::L0) {
     const int base = (tid / NZ) * S::SY + (tid % NZ);
     T v[NX];
 #pragma unroll
-    for (int r = 0; r < NX; r++) v[r] = L[base + r * S::SX];
+    for (int r = 0; r < NX; r++) v[r] = gs[r * (NY * NZ) + tid];
     const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
     apply_shift<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; },
                        [&](int r) { return L[base + r * S::SX]; });
@@ -294,29 +279,43 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
     for (int r = 0; r < NX; r++) L[base + r * S::SX] = v[r];
   }
   __syncthreads();
-  if (tid < S::L1) {  // vy lines: (jx, jz)
-    const int base = (tid / NZ) * S::SX + (tid % NZ);
-    T v[NY];
-#pragma unroll
-    for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
-    const LineCoef<T> k = pfc_line<T, NY>(v, nuy, false);
-    apply_shift<T, NY>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; },
-                       [&](int r) { return L[base + r * S::SY]; });
-#pragma unroll
-    for (int r = 0; r < NY; r++) L[base + r * S::SY] = v[r];
+  for (int rep = 0; rep < REPS; rep++) {
+    if (rep > 0 && tid < S::L0) {  // vx lines: (jy, jz), from LDS on the second repetition
+      const int base = (tid / NZ) * S::SY + (tid % NZ);
+      T v[NX];
+  #pragma unroll
+      for (int r = 0; r < NX; r++) v[r] = L[base + r * S::SX];
+      const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
+      apply_shift<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; },
+                         [&](int r) { return L[base + r * S::SX]; });
+  #pragma unroll
+      for (int r = 0; r < NX; r++) L[base + r * S::SX] = v[r];
+    }
+    __syncthreads();
+    if (tid < S::L1) {  // vy lines: (jx, jz)
+      const int base = (tid / NZ) * S::SX + (tid % NZ);
+      T v[NY];
+  #pragma unroll
+      for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
+      const LineCoef<T> k = pfc_line<T, NY>(v, nuy, false);
+      apply_shift<T, NY>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; },
+                         [&](int r) { return L[base + r * S::SY]; });
+  #pragma unroll
+      for (int r = 0; r < NY; r++) L[base + r * S::SY] = v[r];
+    }
+    __syncthreads();
+    if (tid < S::L2) {  // vz lines: (jx, jy)
+      const int base = (tid / NY) * S::SX + (tid % NY) * S::SY;
+      T v[NZ];
+  #pragma unroll
+      for (int r = 0; r < NZ; r++) v[r] = L[base + r];
+      const LineCoef<T> k = pfc_line<T, NZ>(v, nuz, false);
+      apply_shift<T, NZ>(v, k.shift, false, [&](int r, T x) { L[base + r] = x; }, [&](int r) { return L[base + r]; });
+  #pragma unroll
+      for (int r = 0; r < NZ; r++) L[base + r] = v[r];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (tid < S::L2) {  // vz lines: (jx, jy)
-    const int base = (tid / NY) * S::SX + (tid % NY) * S::SY;
-    T v[NZ];
-#pragma unroll
-    for (int r = 0; r < NZ; r++) v[r] = L[base + r];
-    const LineCoef<T> k = pfc_line<T, NZ>(v, nuz, false);
-    apply_shift<T, NZ>(v, k.shift, false, [&](int r, T x) { L[base + r] = x; }, [&](int r) { return L[base + r]; });
-#pragma unroll
-    for (int r = 0; r < NZ; r++) L[base + r] = v[r];
-  }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int i = tid + k * S::THREADS;
@@ -336,7 +335,88 @@ hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
   using S = KickShape<T, NV, NV, NV>;
   static_assert(S::fits, "velocity block does not fit the LDS");
   if (a.np <= 0) return hipSuccess;
-  hipLaunchKernelGGL((kick_block<T, NV, NV, NV>), dim3((unsigned)a.np), dim3(S::THREADS), 0, s, a);
+  if (a.reps == 2)
+    hipLaunchKernelGGL((kick_block<T, NV, NV, NV, 2>), dim3((unsigned)a.np), dim3(S::THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((kick_block<T, NV, NV, NV, 1>), dim3((unsigned)a.np), dim3(S::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---- one-pass drift along z, then y -----------------------------------------
+// A workgroup takes one x index and W consecutive velocity cells of every
+// (y, z) cell (W contiguous values per (y, z) cell in HBM, one or more whole
+// cache lines). Each z line of that tile is read from HBM by one lane, updated
+// in registers and parked in LDS; after a barrier each y line is taken from
+// LDS by one lane, updated and written back to HBM. f crosses HBM once for the
+// two sweeps. Rows of W are unpadded; planes are padded to SY = W (mod 64)
+// elements so both sweep directions are bank-conflict free.
+template <typename T, int NY, int NZ, int W>
+struct DriftShape {
+  static constexpr int SY0 = NZ * W;
+  static constexpr int SY = SY0 + ((((W - SY0) % 64) + 64) % 64);
+  static constexpr int ELEMS = NY * SY;
+  static constexpr int BYTES = ELEMS * (int)sizeof(T);
+  static constexpr int LZ = NY * W, LY = NZ * W;
+  static constexpr int THREADS = ((LZ > LY ? LZ : LY) + 63) / 64 * 64;
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && (W % (16 / (int)sizeof(T))) == 0;
+};
+
+template <typename T, int NY, int NZ, int W>
+__global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_block(DriftArgs a)
+{
+  using S = DriftShape<T, NY, NZ, W>;
+  __shared__ T L[S::ELEMS];
+  const int tid = threadIdx.x;
+  const long long nchunk = a.nv3 / W;
+  const long long ix = blockIdx.x / nchunk;
+  const long long jc = blockIdx.x - ix * nchunk;
+  T* f = static_cast<T*>(a.f) + ix * NY * NZ * a.nv3 + jc * W;   // (y, z, w) = f[(y*NZ + z)*nv3 + w]
+  const bool periodic = a.periodic != 0;
+  // z lines, lane (iy, w): straight from HBM (each row of a wave is whole
+  // cache lines), updated in registers, written into the LDS tile
+  if (tid < S::LZ) {
+    const int iy = tid / W, w = tid - iy * W;
+    const long long jz = (jc * W + w) % a.nvz;
+    const double nu = (a.vmin_z + ((double)jz + 0.5) * a.dv_z) * a.scale_z;
+    const T* src = f + (long long)iy * NZ * a.nv3 + w;
+    T v[NZ];
+#pragma unroll
+    for (int r = 0; r < NZ; r++) v[r] = src[(long long)r * a.nv3];
+    const int base = iy * S::SY + w;
+    const LineCoef<T> k = pfc_line<T, NZ>(v, nu, periodic);
+    apply_shift<T, NZ>(v, k.shift, periodic, [&](int r, T x) { L[base + r * W] = x; },
+                       [&](int r) { return L[base + r * W]; });
+#pragma unroll
+    for (int r = 0; r < NZ; r++) L[base + r * W] = v[r];
+  }
+  __syncthreads();
+  // y lines, lane (iz, w): from the LDS tile, updated in registers, written
+  // straight back to HBM
+  if (tid < S::LY) {
+    const int iz = tid / W, w = tid - iz * W;
+    const long long jy = ((jc * W + w) / a.nvz) % a.nvy;
+    const double nu = (a.vmin_y + ((double)jy + 0.5) * a.dv_y) * a.scale_y;
+    const int base = iz * W + w;
+    T v[NY];
+#pragma unroll
+    for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
+    const LineCoef<T> k = pfc_line<T, NY>(v, nu, periodic);
+    apply_shift<T, NY>(v, k.shift, periodic, [&](int r, T x) { L[base + r * S::SY] = x; },
+                       [&](int r) { return L[base + r * S::SY]; });
+    T* dst = f + (long long)iz * a.nv3 + w;
+#pragma unroll
+    for (int r = 0; r < NY; r++) dst[(long long)r * NZ * a.nv3] = v[r];
+  }
+}
+
+template <typename T, int NP, int W>
+hipError_t launch_drift_yz_sq(const DriftArgs& a, hipStream_t s)
+{
+  using S = DriftShape<T, NP, NP, W>;
+  static_assert(S::fits, "tile does not fit the LDS");
+  const long long blocks = a.nx * (a.nv3 / W);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((drift_yz_block<T, NP, NP, W>), dim3((unsigned)blocks), dim3(S::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -412,6 +492,41 @@ bool kick_fused_supported(int dtype, const int nv[3])
   const int n = nv[0];
   if (dtype == 0) return n == 8 || n == 16 || n == 24 || n == 32;
   return n == 8 || n == 16 || n == 24;
+}
+
+// (y, z) planes of 16, 24 or 32 cells with whole-cache-line velocity chunks
+static int drift_yz_width(int dtype, int ny, int nz, long long nv3)
+{
+  if (ny != nz) return 0;
+  int w = 0;
+  if (dtype == 0) w = (ny == 16) ? 64 : (ny == 24 || ny == 32) ? 32 : 0;
+  else w = (ny == 16) ? 32 : (ny == 24 || ny == 32) ? 16 : 0;
+  if (w == 0 || nv3 % w != 0) return 0;
+  return w;
+}
+
+bool drift_yz_supported(int dtype, int ny, int nz, long long nv3) { return drift_yz_width(dtype, ny, nz, nv3) != 0; }
+
+hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
+{
+  const int w = drift_yz_width(dtype, a.ny, a.nz, a.nv3);
+  if (dtype == 0) {
+    switch (a.ny) {
+      case 16: return launch_drift_yz_sq<float, 16, 64>(a, s);
+      case 24: return launch_drift_yz_sq<float, 24, 32>(a, s);
+      case 32: return launch_drift_yz_sq<float, 32, 32>(a, s);
+      default: break;
+    }
+  } else {
+    switch (a.ny) {
+      case 16: return launch_drift_yz_sq<double, 16, 32>(a, s);
+      case 24: return launch_drift_yz_sq<double, 24, 16>(a, s);
+      case 32: return launch_drift_yz_sq<double, 32, 16>(a, s);
+      default: break;
+    }
+  }
+  (void)w;
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)

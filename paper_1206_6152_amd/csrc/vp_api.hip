@@ -323,32 +323,61 @@ int accel_adjoint(vp_ctx* c, const double* lam_a, void* lam)
   return VP_OK;
 }
 
-// T_vz T_vy T_vx(tau): one pass when the velocity block fits on chip.
-int kick(vp_ctx* c, double tau)
+// T_vz T_vy T_vx(tau), reps times in a row with the same acceleration: one
+// pass over f when the velocity block fits on chip.
+int kick_n(vp_ctx* c, double tau, int reps)
 {
   const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
   if (vp::kick_fused_supported(c->cfg.dtype, nv)) {
     vp::KickArgs a{};
     a.f = c->f;
     a.np = c->np;
+    a.reps = reps;
     for (int l = 0; l < 3; l++) {
       a.a[l] = c->accel + (long long)l * c->np;
       a.scale[l] = tau / c->dv[l];
     }
-    PhaseScope scope(c, 7);
+    PhaseScope scope(c, reps == 2 ? 8 : 7);
     LAUNCH(c, vp::launch_kick(a, c->cfg.dtype, nv, c->stream));
     return VP_OK;
   }
   int r;
-  if ((r = sweep(c, 3, tau)) || (r = sweep(c, 4, tau)) || (r = sweep(c, 5, tau))) return r;
+  for (int i = 0; i < reps; i++)
+    if ((r = sweep(c, 3, tau)) || (r = sweep(c, 4, tau)) || (r = sweep(c, 5, tau))) return r;
   return VP_OK;
 }
 
+int kick(vp_ctx* c, double tau) { return kick_n(c, tau, 1); }
+
+// T_x T_y T_z(tau): z and y in one pass when the (y, z) plane fits on chip
 int drift(vp_ctx* c, double tau)
 {
   int r;
-  if ((r = sweep(c, 2, tau)) || (r = sweep(c, 1, tau)) || (r = sweep(c, 0, tau))) return r;
-  return VP_OK;
+  const auto& k = c->cfg;
+  if (vp::drift_yz_supported(k.dtype, k.n[1], k.n[2], c->nv3)) {
+    vp::DriftArgs a{};
+    a.f = c->f;
+    a.nx = k.n[0];
+    a.nv3 = c->nv3;
+    a.ny = k.n[1];
+    a.nz = k.n[2];
+    a.nvy = k.nv[1];
+    a.nvz = k.nv[2];
+    a.periodic = (k.bc == VP_BC_PERIODIC) ? 1 : 0;
+    a.vmin_y = k.vmin[1];
+    a.dv_y = c->dv[1];
+    a.scale_y = tau / c->dx[1];
+    a.vmin_z = k.vmin[2];
+    a.dv_z = c->dv[2];
+    a.scale_z = tau / c->dx[2];
+    {
+      PhaseScope scope(c, 9);
+      LAUNCH(c, vp::launch_drift_yz(a, k.dtype, c->stream));
+    }
+  } else if ((r = sweep(c, 2, tau)) || (r = sweep(c, 1, tau))) {
+    return r;
+  }
+  return sweep(c, 0, tau);
 }
 
 int check_ctx(vp_ctx* c)
@@ -498,8 +527,15 @@ int vp_run(vp_ctx* c, int32_t nsteps, double dt)
   if (r) return r;
   if (nsteps < 0) return fail(VP_EINVAL, "nsteps must be >= 0");
   if (!(std::isfinite(dt) && dt > 0)) return fail(VP_EINVAL, "dt must be finite and > 0");
-  for (int i = 0; i < nsteps; i++)
-    if ((r = vp_step(c, dt))) return r;
+  if (nsteps == 0) return VP_OK;
+  // the closing half kick of a step and the opening half kick of the next use
+  // the same acceleration and run back to back: one pass does both
+  const double h = 0.5 * dt;
+  if ((r = kick(c, h))) return r;
+  for (int i = 0; i < nsteps; i++) {
+    if ((r = drift(c, dt)) || (r = compute_accel(c))) return r;
+    if ((r = kick_n(c, h, i + 1 < nsteps ? 2 : 1))) return r;
+  }
   return VP_OK;
 }
 

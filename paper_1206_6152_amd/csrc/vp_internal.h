@@ -41,11 +41,26 @@ struct KickArgs {
   long long np;
   const double* a[3];
   double scale[3];
+  int reps;   // 1: one half kick; 2: two consecutive half kicks with the same acceleration
 };
 
 // True when a one-pass kernel exists for this velocity grid and element type.
 bool kick_fused_supported(int dtype, const int nv[3]);
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
+
+// T_y T_z(tau) (z first) in one pass: tile = one x index x W velocity cells of
+// every (y, z) cell. Position sweeps: nu = v_l(j) tau / dx_l.
+struct DriftArgs {
+  void* f;
+  long long nx, nv3;
+  int ny, nz;
+  long long nvy, nvz;
+  int periodic;
+  double vmin_y, dv_y, scale_y;
+  double vmin_z, dv_z, scale_z;
+};
+bool drift_yz_supported(int dtype, int ny, int nz, long long nv3);
+hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s);
 
 // ---- gravity and reductions (FP64) ----------------------------------------
 

@@ -98,3 +98,63 @@ def test_drift_equals_three_sweeps_and_oracle(bc, dtype):
     for ax in (2, 1, 0):
         ref = oracle.sweep(g, ref, ax, tau)
     assert rel_l1(out, ref) <= (1e-14 if dtype == VP_F64 else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
+@pytest.mark.parametrize("plane", [16, 24, 32])
+@pytest.mark.parametrize("nu_max", [0.7, 2.4])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+def test_one_pass_drift_planes(plane, dtype, nu_max, bc):
+    # square (y, z) planes take the one-pass T_y T_z; it must equal the single
+    # sweeps bit for bit and the oracle within tolerance
+    print("case", plane, dtype, nu_max, bc, flush=True)
+    w = small_workload(bc, n=(2, plane, plane), nv=(4, 4, 8))
+    w = w.__class__(name="d", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
+                    vmax=(1.5, 2.0, 1.5), G=1.0, bc=bc)
+    rng = np.random.default_rng(plane)
+    f0 = (structured_f(w.shape, seed=plane) + 1e-3 * rng.uniform(0, 1, w.shape)).astype(NP[dtype]).astype(np.float64)
+    a = np.zeros((3,) + w.n)
+    tau = nu_max * 0.25 / 2.0
+    sim, f = _sim(w, f0, dtype, a)
+    sim.drift(tau)
+    out = f.cpu().numpy()
+    sim.close()
+    sim, f = _sim(w, f0, dtype, a)
+    for ax in (2, 1, 0):
+        sim.sweep(ax, tau)
+    split = f.cpu().numpy()
+    sim.close()
+    assert np.array_equal(out, split)
+    g = oracle_grid(w)
+    ref = f0
+    for ax in (2, 1, 0):
+        ref = oracle.sweep(g, ref, ax, tau)
+    assert rel_l1(out, ref) <= (1e-14 if dtype == VP_F64 else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
+@pytest.mark.parametrize("shape", [((4, 16, 16), (16, 16, 16)), ((2, 6, 4), (8, 8, 8)), ((2, 3, 4), (8, 12, 16))])
+def test_run_equals_repeated_steps(shape, dtype):
+    # vp_run merges the closing and opening half kicks of consecutive steps;
+    # the result must be the same bits as separate vp_step calls
+    n, nv = shape
+    from paper_1206_6152_amd import inputs
+    s = inputs.jeans_sigma(0.5, 2 * np.pi)
+    w = inputs.Workload(name="r", n=n, nv=nv, L=tuple(x / 16.0 for x in n), vmin=(-4 * s,) * 3, vmax=(4 * s,) * 3,
+                        G=1.0, bc=VP_BC_PERIODIC, dt=0.02, steps=4, params=dict(sigma=s, amp=0.05))
+    f0 = inputs.initial_f(w)
+    f0 *= 1 + 0.05 * np.random.default_rng(1).standard_normal(w.n).reshape(w.n + (1, 1, 1))
+    import torch
+    outs = []
+    for mode in ("run", "step"):
+        f = torch.from_numpy(np.ascontiguousarray(f0.astype(NP[dtype]))).to("cuda:0")
+        sim = Simulator(config_of(w, dtype), f)
+        if mode == "run":
+            sim.run(w.steps, w.dt)
+        else:
+            for _ in range(w.steps):
+                sim.step(w.dt)
+        outs.append((f.cpu().numpy(), sim.get_accel().cpu().numpy()))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
