@@ -53,7 +53,8 @@ __device__ __forceinline__ double fma_(double a, double b, double c) { return __
 // this routine produce the same bits:
 //   h = 2 f_k, r = 2 f_inf - h (= 2 (f_inf - f_k) exactly),
 //   Lp = med3(f_{k+1} - f_k, -r, h), Lm = med3(f_k - f_{k-1}, -h, r),
-//   F_k = alpha * fma(c2, Lm, fma(c1, Lp, f_k)),  g_k = (f_k + F_{k-1}) - F_k.
+//   q_k = fma(c2, Lm, fma(c1, Lp, f_k))   (the face flux is F_k = alpha q_k),
+//   g_k = fma(alpha, q_{k-1} - q_k, f_k)   (= f_k + F_{k-1} - F_k).
 template <typename T, int N, bool REV>
 __device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool periodic)
 {
@@ -65,7 +66,7 @@ __device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool pe
   const T twoinf = finf + finf;
 
   // flux through the left face of cell 0: zero (outflow) or that of cell N-1
-  T fprev = T(0);
+  T qprev = T(0);
   T dm = periodic ? AT(0) - AT(N - 1) : AT(0);   // f_0 - f_{-1}
   if (periodic) {
     const T fl = AT(N >= 2 ? N - 2 : 0), f0 = AT(N - 1), fr = AT(0);
@@ -73,7 +74,7 @@ __device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool pe
     const T r = twoinf - h;
     const T lp = clamp_ordered(fr - f0, -r, h);
     const T lm = clamp_ordered(f0 - fl, -h, r);
-    fprev = alpha * fma_(c2, lm, fma_(c1, lp, f0));
+    qprev = fma_(c2, lm, fma_(c1, lp, f0));
   }
   const T ghost_r = periodic ? AT(0) : T(0);
 #pragma unroll
@@ -85,9 +86,9 @@ __device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool pe
     const T r = twoinf - h;
     const T lp = clamp_ordered(dp, -r, h);
     const T lm = clamp_ordered(dm, -h, r);
-    const T F = alpha * fma_(c2, lm, fma_(c1, lp, f0));
-    AT(i) = (f0 + fprev) - F;
-    fprev = F;
+    const T q = fma_(c2, lm, fma_(c1, lp, f0));
+    AT(i) = fma_(alpha, qprev - q, f0);
+    qprev = q;
     dm = dp;
   }
 #undef AT
@@ -124,6 +125,40 @@ __device__ __forceinline__ LineCoef<T> pfc_line(T (&v)[N], double nu, bool perio
     }
   }
   return k;
+}
+
+// Writes the shifted line f'_i = g_{i-s} (periodic wrap, or zero where the
+// source lies beyond an outflow boundary) of the fractional result g held in
+// v to the line's storage; st(i, x) sets cell i. Each cell is written once
+// with its final value.
+template <typename T, int N, typename ST>
+__device__ __forceinline__ void store_shifted(const T (&v)[N], int shift, bool periodic, ST st)
+{
+  if (shift == 0) {
+#pragma unroll
+    for (int r = 0; r < N; r++) st(r, v[r]);
+    return;
+  }
+  // a per-lane copy: the bounds tests below stay inside this rarely taken
+  // branch instead of being precomputed as scalar masks for the whole kernel
+  asm volatile("" : "+v"(shift));
+#pragma unroll
+  for (int r = 0; r < N; r++) {
+    int d = r + shift;
+    if (periodic) {
+      d %= N;
+      if (d < 0) d += N;
+      st(d, v[r]);
+    } else if (d >= 0 && d < N) {
+      st(d, v[r]);
+    }
+  }
+  if (!periodic) {
+    for (int i = 0; i < N; i++) {
+      const int src = i - shift;
+      if (src < 0 || src >= N) st(i, T(0));
+    }
+  }
 }
 
 // f'_i = g_{i-s}: the fractional result g goes to the line's storage, then

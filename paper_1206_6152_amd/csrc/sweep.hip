@@ -59,10 +59,7 @@ __global__ __launch_bounds__(256) void sweep_strided_wide(SweepArgs a)
 #pragma unroll
   for (int r = 0; r < N; r++) v[r] = p[(long long)r * inner];
   const LineCoef<T> k = pfc_line<T, N>(v, line_nu_wide(a, o, c), a.periodic != 0);
-  apply_shift<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { p[(long long)r * inner] = x; },
-                    [&](int r) { return p[(long long)r * inner]; });
-#pragma unroll
-  for (int r = 0; r < N; r++) p[(long long)r * inner] = v[r];
+  store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { p[(long long)r * inner] = x; });
 }
 
 // Strided lines, compact addressing: the workgroup's first line is the uniform
@@ -96,10 +93,7 @@ __global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
 #pragma unroll
   for (int r = 0; r < N; r++) v[r] = (fb + (long long)r * inner)[off];
   const LineCoef<T> k = pfc_line<T, N>(v, nu, a.periodic != 0);
-  apply_shift<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { (fb + (long long)r * inner)[off] = x; },
-                    [&](int r) { return (fb + (long long)r * inner)[off]; });
-#pragma unroll
-  for (int r = 0; r < N; r++) (fb + (long long)r * inner)[off] = v[r];
+  store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { (fb + (long long)r * inner)[off] = x; });
 }
 
 template <typename T, int N>
@@ -189,9 +183,7 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
 #pragma unroll
     for (int r = 0; r < N; r++) v[r] = row[r];
     const LineCoef<T> k = pfc_line<T, N>(v, nu, a.periodic != 0);
-    apply_shift<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { row[r] = x; }, [&](int r) { return row[r]; });
-#pragma unroll
-    for (int r = 0; r < N; r++) row[r] = v[r];
+    store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { row[r] = x; });
   }
   __syncthreads();
   if (nl == LINES) {
@@ -273,10 +265,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
 #pragma unroll
     for (int r = 0; r < NX; r++) v[r] = gs[r * (NY * NZ) + tid];
     const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
-    apply_shift<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; },
-                       [&](int r) { return L[base + r * S::SX]; });
-#pragma unroll
-    for (int r = 0; r < NX; r++) L[base + r * S::SX] = v[r];
+    store_shifted<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
   }
   __syncthreads();
   for (int rep = 0; rep < REPS; rep++) {
@@ -286,10 +275,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
   #pragma unroll
       for (int r = 0; r < NX; r++) v[r] = L[base + r * S::SX];
       const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
-      apply_shift<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; },
-                         [&](int r) { return L[base + r * S::SX]; });
-  #pragma unroll
-      for (int r = 0; r < NX; r++) L[base + r * S::SX] = v[r];
+      store_shifted<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
     }
     __syncthreads();
     if (tid < S::L1) {  // vy lines: (jx, jz)
@@ -298,10 +284,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
   #pragma unroll
       for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
       const LineCoef<T> k = pfc_line<T, NY>(v, nuy, false);
-      apply_shift<T, NY>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; },
-                         [&](int r) { return L[base + r * S::SY]; });
-  #pragma unroll
-      for (int r = 0; r < NY; r++) L[base + r * S::SY] = v[r];
+      store_shifted<T, NY>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; });
     }
     __syncthreads();
     if (tid < S::L2) {  // vz lines: (jx, jy)
@@ -310,9 +293,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
   #pragma unroll
       for (int r = 0; r < NZ; r++) v[r] = L[base + r];
       const LineCoef<T> k = pfc_line<T, NZ>(v, nuz, false);
-      apply_shift<T, NZ>(v, k.shift, false, [&](int r, T x) { L[base + r] = x; }, [&](int r) { return L[base + r]; });
-  #pragma unroll
-      for (int r = 0; r < NZ; r++) L[base + r] = v[r];
+      store_shifted<T, NZ>(v, k.shift, false, [&](int r, T x) { L[base + r] = x; });
     }
     __syncthreads();
   }
@@ -384,10 +365,7 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
     for (int r = 0; r < NZ; r++) v[r] = src[(long long)r * a.nv3];
     const int base = iy * S::SY + w;
     const LineCoef<T> k = pfc_line<T, NZ>(v, nu, periodic);
-    apply_shift<T, NZ>(v, k.shift, periodic, [&](int r, T x) { L[base + r * W] = x; },
-                       [&](int r) { return L[base + r * W]; });
-#pragma unroll
-    for (int r = 0; r < NZ; r++) L[base + r * W] = v[r];
+    store_shifted<T, NZ>(v, k.shift, periodic, [&](int r, T x) { L[base + r * W] = x; });
   }
   __syncthreads();
   // y lines, lane (iz, w): from the LDS tile, updated in registers, written
@@ -401,11 +379,8 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
 #pragma unroll
     for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
     const LineCoef<T> k = pfc_line<T, NY>(v, nu, periodic);
-    apply_shift<T, NY>(v, k.shift, periodic, [&](int r, T x) { L[base + r * S::SY] = x; },
-                       [&](int r) { return L[base + r * S::SY]; });
     T* dst = f + (long long)iz * a.nv3 + w;
-#pragma unroll
-    for (int r = 0; r < NY; r++) dst[(long long)r * NZ * a.nv3] = v[r];
+    store_shifted<T, NY>(v, k.shift, periodic, [&](int r, T x) { dst[(long long)r * NZ * a.nv3] = x; });
   }
 }
 

@@ -50,6 +50,7 @@ struct vp_ctx {
   void* f = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;
+  int ncu = 0;                // compute units of the device (persistent one-pass kernels)
   long long np = 0, nv3 = 0;
   double dx[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
   Grid3 ng{};           // spatial grid
@@ -436,7 +437,12 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
   c->cfg = *cfg;
   c->f = f_dev;
   c->stream = (hipStream_t)hip_stream;
-  hipGetDevice(&c->device);
+  hipError_t de = hipGetDevice(&c->device);
+  if (de == hipSuccess) de = hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (de != hipSuccess) {
+    delete c;
+    return fail(VP_EHIP, "device query: %s", hipGetErrorString(de));
+  }
   for (int l = 0; l < 3; l++) {
     c->dx[l] = cfg->L[l] / cfg->n[l];
     c->dv[l] = (cfg->vmax[l] - cfg->vmin[l]) / cfg->nv[l];
