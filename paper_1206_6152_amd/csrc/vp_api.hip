@@ -50,7 +50,6 @@ struct vp_ctx {
   void* f = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;
-  int ncu = 0;                // compute units of the device (persistent one-pass kernels)
   long long np = 0, nv3 = 0;
   double dx[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
   Grid3 ng{};           // spatial grid
@@ -437,8 +436,7 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
   c->cfg = *cfg;
   c->f = f_dev;
   c->stream = (hipStream_t)hip_stream;
-  hipError_t de = hipGetDevice(&c->device);
-  if (de == hipSuccess) de = hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  const hipError_t de = hipGetDevice(&c->device);
   if (de != hipSuccess) {
     delete c;
     return fail(VP_EHIP, "device query: %s", hipGetErrorString(de));
