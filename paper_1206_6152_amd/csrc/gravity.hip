@@ -88,6 +88,21 @@ __global__ __launch_bounds__(RED) void density_kernel(const T* f, double* rho, l
   if (threadIdx.x == 0) rho[blockIdx.x] = s * dv3;
 }
 
+// One thread per spatial cell (x, yz), x fastest so a wave reads whole rows of
+// the workgroup sums; the velocity chunks are added in their index order.
+__global__ __launch_bounds__(256) void density_from_parts_kernel(double* rho, const double* part, long long nyz,
+                                                                 long long nchunk, int n, double dv3)
+{
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nyz * n) return;
+  const long long yz = i / n;
+  const int x = (int)(i - yz * n);
+  const double* p = part + yz * nchunk * n + x;
+  double acc = 0.0;
+  for (long long k = 0; k < nchunk; k++) acc += p[k * n];
+  rho[(long long)x * nyz + yz] = acc * dv3;
+}
+
 __global__ void twiddle_kernel(double2* w, int M)
 {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -515,6 +530,16 @@ hipError_t launch_density(const void* f, int dtype, double* rho, long long np, l
     hipLaunchKernelGGL(density_kernel<float>, dim3((unsigned)np), dim3(RED), 0, s, (const float*)f, rho, nv3, dv3);
   else
     hipLaunchKernelGGL(density_kernel<double>, dim3((unsigned)np), dim3(RED), 0, s, (const double*)f, rho, nv3, dv3);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_from_parts(double* rho, const double* part, long long nyz, long long nchunk, int n,
+                                     double dv3, hipStream_t s)
+{
+  const long long cells = nyz * n;
+  if (cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(density_from_parts_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, rho, part,
+                     nyz, nchunk, n, dv3);
   return hipGetLastError();
 }
 

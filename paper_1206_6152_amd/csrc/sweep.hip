@@ -65,7 +65,18 @@ __global__ __launch_bounds__(256) void sweep_strided_wide(SweepArgs a)
 // Strided lines, compact addressing: the workgroup's first line is the uniform
 // base; a lane's cells sit at base + r*inner + off with a 32-bit offset (the
 // host checks that every offset fits), and the line index arithmetic is 32-bit.
+// PART (x sweep, 256 lines of one spatial (y, z) column per workgroup): the
+// workgroup also sums its lines' new values at each x in FP64, in a fixed
+// order, into part[blockIdx.x * N + x], so the density needs no extra pass
+// over f.
 template <typename T, int N>
+struct PartShape {
+  static constexpr int ROW = 256 + 8;   // padded LDS row: the reads below hit distinct banks
+  static constexpr int P = 256 / N;      // lanes that share one row's sum
+  static constexpr bool ok = N >= 4 && N <= 64 && 256 % N == 0 && N * ROW * (int)sizeof(T) <= 68 * 1024;
+};
+
+template <typename T, int N, bool PART>
 __global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
 {
   const long long gid0 = (long long)blockIdx.x * 256;
@@ -94,6 +105,20 @@ __global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
   for (int r = 0; r < N; r++) v[r] = (fb + (long long)r * inner)[off];
   const LineCoef<T> k = pfc_line<T, N>(v, nu, a.periodic != 0);
   store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { (fb + (long long)r * inner)[off] = x; });
+  if constexpr (PART) {
+    // every lane of the workgroup is live here (the host checks it)
+    using PS = PartShape<T, N>;
+    __shared__ T tile[N * PS::ROW];   // row r: the new values at x = r of the 256 lines
+    store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { tile[r * PS::ROW + t] = x; });
+    __syncthreads();
+    const int row = t / PS::P, q = t % PS::P;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) acc += (double)tile[row * PS::ROW + j * PS::P + q];
+#pragma unroll
+    for (int o = PS::P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (q == 0) a.part[(long long)blockIdx.x * N + row] = acc;
+  }
 }
 
 template <typename T, int N>
@@ -395,6 +420,16 @@ hipError_t launch_drift_yz_sq(const DriftArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
+// compact addressing when every lane offset from its workgroup's first line
+// fits in 31 bits and the index arithmetic fits in 32 bits
+bool narrow_ok(const SweepArgs& a, int N)
+{
+  const bool no_straddle = (a.inner % 256) == 0;
+  const long long span = no_straddle ? 256 : (256 / a.inner + 2) * (long long)N * a.inner;
+  return a.inner < (1LL << 31) && span < (1LL << 31) && a.j_div < (1LL << 31) && a.j_mod < (1LL << 31) &&
+         a.sp_div < (1LL << 31);
+}
+
 template <typename T, int N>
 hipError_t launch_n(const SweepArgs& a, hipStream_t s)
 {
@@ -405,14 +440,16 @@ hipError_t launch_n(const SweepArgs& a, hipStream_t s)
     hipLaunchKernelGGL((sweep_contig<T, N>), dim3((unsigned)blocks), dim3(LINES), 0, s, a);
   } else {
     const long long blocks = (a.nlines + 255) / 256;
-    // compact addressing when every lane offset from its workgroup's first
-    // line fits in 31 bits and the index arithmetic fits in 32 bits
-    const bool no_straddle = (a.inner % 256) == 0;
-    const long long span = no_straddle ? 256 : (256 / a.inner + 2) * (long long)N * a.inner;
-    const bool narrow = a.inner < (1LL << 31) && span < (1LL << 31) && a.j_div < (1LL << 31) &&
-                        a.j_mod < (1LL << 31) && a.sp_div < (1LL << 31);
-    if (narrow)
-      hipLaunchKernelGGL((sweep_strided<T, N>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const bool narrow = narrow_ok(a, N);
+    if (narrow && a.part) {
+      if constexpr (PartShape<T, N>::ok)
+        hipLaunchKernelGGL((sweep_strided<T, N, true>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+      else
+        return hipErrorInvalidValue;
+    } else if (a.part) {
+      return hipErrorInvalidValue;
+    } else if (narrow)
+      hipLaunchKernelGGL((sweep_strided<T, N, false>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     else
       hipLaunchKernelGGL((sweep_strided_wide<T, N>), dim3((unsigned)blocks), dim3(256), 0, s, a);
   }
@@ -442,6 +479,26 @@ hipError_t launch_t(const SweepArgs& a, hipStream_t s)
 }
 
 }  // namespace
+
+template <typename T>
+bool part_shape_ok(int n)
+{
+  switch (n) {
+    case 4: return PartShape<T, 4>::ok;
+    case 8: return PartShape<T, 8>::ok;
+    case 16: return PartShape<T, 16>::ok;
+    case 32: return PartShape<T, 32>::ok;
+    case 64: return PartShape<T, 64>::ok;
+    default: return false;
+  }
+}
+
+bool sweep_part_supported(const SweepArgs& a, int dtype)
+{
+  // whole workgroups of lines (no lane leaves early), strided lines, compact addressing
+  if (a.inner % 256 != 0 || a.nlines % 256 != 0 || !narrow_ok(a, a.n)) return false;
+  return dtype == 0 ? part_shape_ok<float>(a.n) : part_shape_ok<double>(a.n);
+}
 
 bool sweep_length_supported(int n)
 {

@@ -68,6 +68,9 @@ struct vp_ctx {
   double* radj = nullptr;     // np
   double* dnu = nullptr;      // one value per line of a sweep
   long long dnu_len = 0;
+  // workgroup sums of the x sweep (density without another pass over f);
+  // null when the x sweep of this grid cannot produce them
+  double* xsum = nullptr;
   // phase timing (vp_profile_*): pending event pairs per phase
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;
@@ -122,6 +125,7 @@ void release(vp_ctx* c)
   hipFree(c->kspec);
   for (auto& t : c->tw) hipFree(t);
   hipFree(c->part);
+  hipFree(c->xsum);
   hipFree(c->red);
   hipFree(c->lphi);
   hipFree(c->radj);
@@ -229,6 +233,15 @@ int compute_accel(vp_ctx* c)
   return VP_OK;
 }
 
+// acceleration of the density held in c->rho
+int accel_from_rho(vp_ctx* c)
+{
+  int r = poisson_from(c, c->rho, c->phi);
+  if (r != VP_OK) return r;
+  LAUNCH(c, vp::launch_gradient(c->accel, c->phi, c->ng, c->dx[0], c->dx[1], c->dx[2], c->stream));
+  return VP_OK;
+}
+
 vp::SweepArgs sweep_args(vp_ctx* c, int axis, double tau)
 {
   const auto& k = c->cfg;
@@ -271,6 +284,14 @@ int sweep(vp_ctx* c, int axis, double tau)
   PhaseScope scope(c, axis);
   LAUNCH(c, vp::launch_sweep(a, c->cfg.dtype, c->stream));
   return VP_OK;
+}
+
+// True when the x sweep can leave per-workgroup density sums: every
+// workgroup's 256 lines lie in one spatial (y, z) column.
+bool x_sweep_sums(vp_ctx* c)
+{
+  const vp::SweepArgs a = sweep_args(c, 0, 1.0);
+  return c->nv3 % 256 == 0 && vp::sweep_part_supported(a, c->cfg.dtype);
 }
 
 // lam <- J^T lam of T_axis(tau) at forward input fin; velocity axes add the
@@ -349,8 +370,9 @@ int kick_n(vp_ctx* c, double tau, int reps)
 
 int kick(vp_ctx* c, double tau) { return kick_n(c, tau, 1); }
 
-// T_x T_y T_z(tau): z and y in one pass when the (y, z) plane fits on chip
-int drift(vp_ctx* c, double tau)
+// T_x T_y T_z(tau): z and y in one pass when the (y, z) plane fits on chip;
+// with x_sums the x sweep also writes its workgroup sums to c->xsum
+int drift(vp_ctx* c, double tau, bool x_sums = false)
 {
   int r;
   const auto& k = c->cfg;
@@ -377,7 +399,30 @@ int drift(vp_ctx* c, double tau)
   } else if ((r = sweep(c, 2, tau)) || (r = sweep(c, 1, tau))) {
     return r;
   }
-  return sweep(c, 0, tau);
+  if (!x_sums) return sweep(c, 0, tau);
+  vp::SweepArgs a = sweep_args(c, 0, tau);
+  a.part = c->xsum;
+  PhaseScope scope(c, 0);
+  LAUNCH(c, vp::launch_sweep(a, c->cfg.dtype, c->stream));
+  return VP_OK;
+}
+
+// drift, then the acceleration of the drifted f (one step's middle): the x
+// sweep sums its new values per workgroup when it can, which replaces the
+// density pass over f by a reduction of those sums
+int drift_accel(vp_ctx* c, double tau)
+{
+  if (!c->xsum) {
+    int r = drift(c, tau);
+    return r ? r : compute_accel(c);
+  }
+  int r = drift(c, tau, /*x_sums=*/true);
+  if (r) return r;
+  PhaseScope scope(c, 6);
+  const long long nyz = (long long)c->cfg.n[1] * c->cfg.n[2];
+  LAUNCH(c, vp::launch_density_from_parts(c->rho, c->xsum, nyz, c->nv3 / 256, c->cfg.n[0],
+                                          c->dv[0] * c->dv[1] * c->dv[2], c->stream));
+  return accel_from_rho(c);
 }
 
 int check_ctx(vp_ctx* c)
@@ -470,6 +515,13 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
     release(c);
     return r;
   }
+  if (x_sweep_sums(c)) {   // n_x sums per 256 lines of the x sweep
+    const long long nsum = (long long)cfg->n[1] * cfg->n[2] * (c->nv3 / 256) * cfg->n[0];
+    if ((r = dalloc(&c->xsum, sizeof(double) * nsum, "x sweep sums"))) {
+      release(c);
+      return r;
+    }
+  }
   hipError_t he = hipHostMalloc((void**)&c->host, sizeof(double) * 8, hipHostMallocDefault);
   if (he != hipSuccess) {
     c->host = nullptr;
@@ -520,7 +572,7 @@ int vp_step(vp_ctx* c, double dt)
   if (r) return r;
   if (!(std::isfinite(dt) && dt > 0)) return fail(VP_EINVAL, "dt must be finite and > 0");
   const double h = 0.5 * dt;
-  if ((r = kick(c, h)) || (r = drift(c, dt)) || (r = compute_accel(c)) || (r = kick(c, h))) return r;
+  if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) return r;
   return VP_OK;
 }
 
@@ -537,7 +589,7 @@ int vp_run(vp_ctx* c, int32_t nsteps, double dt)
   const double h = 0.5 * dt;
   if ((r = kick(c, h))) return r;
   for (int i = 0; i < nsteps; i++) {
-    if ((r = drift(c, dt)) || (r = compute_accel(c))) return r;
+    if ((r = drift_accel(c, dt))) return r;
     if ((r = kick_n(c, h, i + 1 < nsteps ? 2 : 1))) return r;
   }
   return VP_OK;
@@ -735,7 +787,7 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   const double h = 0.5 * dt;
   for (int n = 0; n < nsteps; n++) {
     if (n % k == 0 && (r = copy_f(c, ck[n / k], user_f, fb))) return r;
-    if ((r = kick(c, h)) || (r = drift(c, dt)) || (r = compute_accel(c)) || (r = kick(c, h))) return r;
+    if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) return r;
     if ((r = copy_f(c, A(n + 1), c->accel, ab))) return r;
   }
   if ((r = copy_f(c, fin, user_f, fb))) return r;
@@ -756,7 +808,7 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
       if ((r = copy_f(c, stepb[n - s0], W, fb))) break;
       if (n + 1 < s1) {
         if ((r = set_accel(n))) break;
-        if ((r = kick(c, h)) || (r = drift(c, dt)) || (r = compute_accel(c)) || (r = kick(c, h))) break;
+        if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) break;
       }
     }
     for (int n = s1 - 1; n >= s0 && r == VP_OK; n--) {

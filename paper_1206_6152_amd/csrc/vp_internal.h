@@ -25,10 +25,16 @@ struct SweepArgs {
   long long j_div;     // velocity index j = (c / j_div) % j_mod (position sweeps)
   long long j_mod;
   double vmin, dv;     // cell-centre velocity v_j = vmin + (j + 1/2) dv
+  double* part;        // optional: per-workgroup sums of the new line values (see below)
 };
 
 // Launch one sweep on the stream; dtype 0 = float, 1 = double.
 hipError_t launch_sweep(const SweepArgs& a, int dtype, hipStream_t s);
+
+// With part set, workgroup b (256 consecutive lines) also writes
+// part[b * n + r] = sum over its lines of the new value at cell r, in FP64.
+// True when the sweep supports that for these arguments.
+bool sweep_part_supported(const SweepArgs& a, int dtype);
 
 // True when n is a line length the sweep kernels are instantiated for.
 bool sweep_length_supported(int n);
@@ -67,6 +73,12 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s);
 // rho[s] = dv3 * sum_j f[s*nv3 + j]
 hipError_t launch_density(const void* f, int dtype, double* rho, long long np, long long nv3,
                           double dv3, hipStream_t s);
+
+// rho from the x sweep's workgroup sums: spatial column yz (of nyz) has
+// nchunk workgroups, each with n sums (one per x);
+// rho[x*nyz + yz] = dv3 * sum_k part[(yz*nchunk + k)*n + x], k in order.
+hipError_t launch_density_from_parts(double* rho, const double* part, long long nyz, long long nchunk, int n,
+                                     double dv3, hipStream_t s);
 
 struct Grid3 {
   int m[3];
