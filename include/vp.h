@@ -95,7 +95,11 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out);
  * T_vx, T_vy, T_vz at dt/2 with the new acceleration. The acceleration left in
  * the context serves the first half kick of the next step, so the Poisson
  * equation is solved once per step, after the position sweeps as the paper
- * states. dt must be finite and > 0. */
+ * states. When Nv^3 is a multiple of 256 and Nx is 4, 8, 16, 32 or 64 (64
+ * only for VP_F32), the T_x sweep also sums its new values over velocity in
+ * FP64 and the density of Eq. (18) comes from those sums (same value as
+ * vp_density up to the order of the FP64 additions). dt must be finite and
+ * > 0. */
 int vp_step(vp_ctx* ctx, double dt);
 
 /* n consecutive vp_step calls with the same dt (n >= 0), with the same result
@@ -156,7 +160,8 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * vp_profile_enable(ctx, 0) stops. vp_profile_read synchronises the stream and
  * returns, per phase, the summed event time in milliseconds and the number of
  * launches: phases 0..5 are the sweeps along x, y, z, vx, vy, vz, phase 6 the
- * gravity solve (density, Poisson, acceleration), phase 7 the one-pass half
+ * gravity solve (density, or the reduction of the T_x sums, Poisson,
+ * acceleration), phase 7 the one-pass half
  * kick, phase 8 the one-pass pair of half kicks of vp_run, phase 9 the
  * one-pass T_y T_z. Arrays have VP_NPHASE entries and are caller-owned host
  * memory. */
