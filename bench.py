@@ -30,6 +30,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E, AMD public specification
+# Vector ALU issue rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-operations/s (= 157.3 TFLOP/s FP32 / 2 for FMA / 2 for packed pairs).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Arithmetic of one cell in one sweep: line maximum (1), f_{k+1} - f_k (1), 2 f_k (1),
+# 2 f_k - 2 f_inf (1), two clamps (2), q_k = fma(c2, Lm, fma(c1, Lp, f_k)) (2),
+# q_{k-1} - q_k (1), g_k = fma(alpha, q_{k-1} - q_k, f_k) (1).
+OPS_PER_CELL_SWEEP = 10
 METRIC = "phase-space cell updates/s (FP32 vs FP64 GPU) + % HBM roofline"
 
 
@@ -104,6 +111,13 @@ PHASE_KERNEL = {
 }
 
 
+def x_sweep_sums(w, elem_bytes):
+    """Whether the x sweep of a step also sums the density (256 velocity cells per
+    workgroup, x lines of 4..64 cells, 32 at most in FP64)."""
+    nv3 = w.nv[0] * w.nv[1] * w.nv[2]
+    return nv3 % 256 == 0 and w.n[0] in ((4, 8, 16, 32, 64) if elem_bytes == 4 else (4, 8, 16, 32))
+
+
 def kernel_name(phase, w, elem_bytes):
     t = "float" if elem_bytes == 4 else "double"
     if phase in ("kick", "kick2"):
@@ -113,8 +127,10 @@ def kernel_name(phase, w, elem_bytes):
         return "vp::drift_yz_block<%s, %d, %d, %d>" % (t, w.n[1], w.n[2], wd)
     axis = ["x", "y", "z", "vx", "vy", "vz"].index(phase)
     n = (list(w.n) + list(w.nv))[axis]
-    kind = "sweep_contig" if axis == 5 else "sweep_strided"
-    return "vp::%s<%s, %d>" % (kind, t, n)
+    if axis == 5:
+        return "vp::sweep_contig<%s, %d>" % (t, n)
+    sums = axis == 0 and x_sweep_sums(w, elem_bytes)
+    return "vp::sweep_strided<%s, %d, %s>" % (t, n, "true" if sums else "false")
 
 
 def gpu_run(w, vp_dtype, steps, warmup):
@@ -146,25 +162,41 @@ def gpu_run(w, vp_dtype, steps, warmup):
     sweep_tot = {k: phases[k][0] for k in ("x", "y", "z", "vx", "vy", "vz", "kick", "kick2", "drift_yz")}
     dom = max(sweep_tot, key=sweep_tot.get)
     dom_ms = per_launch[dom]
-    sweep_bytes = 2.0 * s * cells          # read + write f once per launch (one sweep or one fused kick)
-    achieved = sweep_bytes / (dom_ms * 1e-3) / 1e9
+    sweep_bytes = 2.0 * s * cells          # read + write f once per launch (one sweep or one fused pass)
+    hbm_gbps = sweep_bytes / (dom_ms * 1e-3) / 1e9
     step_ms = wall * 1e3 / steps
     step_bytes = 19.0 * s * cells          # 9 sweeps x 2 + one density read
+    # what a step of this build must move: every pass over f reads and writes it once
+    passes = sum(n for k, (ms, n) in phases.items() if k not in ("gravity",)) / max(1, steps)
+    fused_bytes = passes * 2.0 * s * cells
     kname = kernel_name(dom, w, s)
     traffic = committed_traffic(w, s, kname)
+    common = dict(kernel=PHASE_KERNEL.get(dom, "pfc sweep along %s" % dom), traffic=traffic,
+                  traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                  hip_kernel=kname, algorithmic_bytes_per_launch=sweep_bytes, avg_launch_ms=dom_ms,
+                  hbm_GBps=hbm_gbps, hbm_frac=hbm_gbps / PEAK_HBM_GBPS)
+    if dom in ("kick", "kick2"):
+        # three (or six) sweeps per pass on data held in LDS: bound by vector ALU issue
+        sweeps = 6 if dom == "kick2" else 3
+        ops = sweeps * OPS_PER_CELL_SWEEP * cells
+        tops = ops / (dom_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=tops, peak=PEAK_VALU_TOPS, unit="T lane-ops/s",
+                    frac=tops / PEAK_VALU_TOPS, algorithmic_ops_per_launch=ops, **common)
+    else:
+        roof = dict(bound="hbm", achieved=hbm_gbps, peak=PEAK_HBM_GBPS, unit="GB/s",
+                    frac=hbm_gbps / PEAK_HBM_GBPS, **common)
     return dict(
         value=cells * steps / wall,
         ms_per_step=step_ms,
         bytes_per_elem=s,
         dominant=dom,
-        roofline=dict(bound="hbm", kernel=PHASE_KERNEL.get(dom, "pfc sweep along %s" % dom), achieved=achieved,
-                      peak=PEAK_HBM_GBPS, unit="GB/s", frac=achieved / PEAK_HBM_GBPS,
-                      traffic=traffic, traffic_unit="bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
-                      "copy-calibrated)", hip_kernel=kname, algorithmic_bytes_per_launch=sweep_bytes,
-                      avg_launch_ms=dom_ms),
+        roofline=roof,
         step_roofline=dict(model_bytes_per_step=step_bytes,
                            achieved_GBps=step_bytes / (step_ms * 1e-3) / 1e9,
-                           frac=step_bytes / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS),
+                           frac=step_bytes / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                           passes_per_step=passes, fused_bytes_per_step=fused_bytes,
+                           fused_GBps=fused_bytes / (step_ms * 1e-3) / 1e9,
+                           fused_frac=fused_bytes / (step_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS),
         phases_ms_per_launch=per_launch,
         phases_launches={k: n for k, (ms, n) in phases.items()},
         copy_GBps=copy_gbps,
@@ -211,6 +243,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-stored run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="profiling aid: run only the FP64-stored case (reported as the value, dtype f64)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -222,6 +256,15 @@ def main():
     w = inputs.WORKLOADS[args.workload]()
     log("workload", w.name, "cells", w.cells, "dt", w.dt)
 
+    if args.fp64_only:
+        r64 = gpu_run(w, VP_F64, args.steps, args.warmup)
+        print(json.dumps({"metric": METRIC, "value": r64["value"], "unit": "cell-updates/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": w.name, "cells": w.cells},
+                          "roofline": r64["roofline"], "step_roofline": r64["step_roofline"],
+                          "phases_ms_per_launch": r64["phases_ms_per_launch"], "cpu_baseline": None}), flush=True)
+        return
     r32 = gpu_run(w, VP_F32, args.steps, args.warmup)
     log("fp32", json.dumps(r32))
     r64 = None
