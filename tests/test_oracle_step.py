@@ -7,7 +7,8 @@ import math
 
 import numpy as np
 import pytest
-from scipy import optimize, special
+from linear_theory import gamma_of, growth_root, mode_amplitude
+from scipy import optimize
 
 from oracle import Grid, Run
 from paper_1206_6152_amd import inputs
@@ -17,21 +18,6 @@ def grid_of(w):
     return Grid(n=w.n, nv=w.nv, L=w.L, vmin=w.vmin, vmax=w.vmax, G=w.G, bc=w.bc)
 
 
-def growth_root(k_over_kj: float) -> float:
-    """y with k^2/k_J^2 = 1 + w Z(w) at w = i y (Eq. (38)); Z(w) = i sqrt(pi) wofz(w)."""
-    def h(y):
-        w = 1j * y
-        return (1 + w * 1j * math.sqrt(math.pi) * special.wofz(w)).real - k_over_kj ** 2
-    if k_over_kj < 1:
-        return optimize.brentq(h, 1e-9, 1e4, xtol=1e-14)
-    return optimize.brentq(h, -5.0, -1e-9, xtol=1e-14)
-
-
-def gamma_of(k_over_kj: float, G=1.0, rho=1.0) -> float:
-    # w = i gamma / (sqrt(8 pi G rho) k/k_J)  (Eq. (40))
-    return growth_root(k_over_kj) * math.sqrt(8 * math.pi * G * rho) * k_over_kj
-
-
 def test_dispersion_roots_known_limits():
     # long-wavelength limit: gamma -> sqrt(4 pi G rho) (fluid Jeans rate)
     assert gamma_of(1e-2) == pytest.approx(math.sqrt(4 * math.pi), rel=1e-3)
@@ -39,13 +25,6 @@ def test_dispersion_roots_known_limits():
     assert abs(growth_root(0.999999)) < 1e-3
     # damped for k > k_J
     assert gamma_of(2.0) < 0
-
-
-def mode_amplitude(rho, m):
-    d = rho / rho.mean() - 1.0
-    n = d.shape[0]
-    x = np.arange(n)
-    return 2 * abs(np.mean(d[:, 0, 0] * np.exp(-2j * np.pi * m * x / n)))
 
 
 def test_free_streaming_integer_shift_full_step(orc):
