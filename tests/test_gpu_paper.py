@@ -1,6 +1,7 @@
-"""The paper's one-dimensional tests (Sec. 3.1-3.3) at its resolution, 128 x 128
-cells of (x, v_x) phase space, run through the C ABI on the GPU as six-dimensional
-grids with one cell on the other four axes.
+"""The paper's Tests 1-4 through the C ABI on the GPU. Tests 1-3 (Sec. 3.1-3.3) at
+the paper's resolution, 128 x 128 cells of (x, v_x) phase space, as six-dimensional
+grids with one cell on the other four axes; Test 4 (Sec. 3.4) in six dimensions,
+64^3 x 32^3 cells in FP32.
 
 Each run is compared with the oracle on the same input (FP64: parity of the
 whole run) and with what the paper and kinetic theory fix:
@@ -12,7 +13,11 @@ whole run) and with what the paper and kinetic theory fix:
           rates of the dispersion relation, Eq. (38), mass within 1e-6 and
           energy within 1e-3 (the paper's bounds);
   Test 3  Galilean invariance: a drift of sigma or 2 sigma leaves |A_2(t)|
-          unchanged.
+          unchanged;
+  Test 4  white-noise density on a Maxwellian with k_J = 16 pi / L: each shell of
+          the density power spectrum grows or damps as exp(2 gamma t) with gamma
+          of Eq. (38) in the linear phase, and the strongest damping falls short
+          of it near k = 2 k_J, as the paper reports.
 Velocity box: +-V with V = L/T = 1 (Sec. 3.2), widened to +-6 sigma where the
 Maxwellian is wider than that (k/k_J = 1.1, 2.0) so that no mass leaves through
 the velocity boundary."""
@@ -160,3 +165,77 @@ def test_3_galilean_invariance(k_over_kj, amp, t_end):
         _, a1, _, _ = _run_1d(VP_F64, k_over_kj, amp, t_end, drift=vt, dt=dt, parity=False)
         print("drift", vt / s, "sigma: max relative change of |A_2|", np.max(np.abs(a1 / a0 - 1)), flush=True)
         np.testing.assert_allclose(a1, a0, rtol=1e-2)
+
+
+def _device_f(w, dtype):
+    """f = (1 + delta(x)) M(v), formed on the device in FP64 and rounded once"""
+    import torch
+    tdt = torch.float32 if dtype == VP_F32 else torch.float64
+    dens, m = inputs.separable_factors(w)
+    d = torch.from_numpy(dens.reshape(-1)).to("cuda:0")
+    mv = torch.from_numpy(m.reshape(-1)).to("cuda:0")
+    f = torch.empty(w.shape, dtype=tdt, device="cuda:0")
+    fv = f.view(d.numel(), mv.numel())
+    step = max(1, (1 << 27) // mv.numel())
+    for i in range(0, d.numel(), step):
+        fv[i:i + step] = (d[i:i + step, None] * mv[None, :]).to(tdt)
+    torch.cuda.synchronize()
+    return f
+
+
+def _shell_power(rho, nmax):
+    """P(k) = <|delta_k|^2> in shells |n| in [s - 1/2, s + 1/2), k = 2 pi n / L"""
+    d = rho / rho.mean() - 1.0
+    p = np.abs(np.fft.fftn(d) / d.size) ** 2
+    ks = np.meshgrid(*[np.fft.fftfreq(s, 1.0 / s) for s in d.shape], indexing="ij")
+    nn = np.sqrt(ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2)
+    shells = np.arange(1, nmax + 1)
+    P = np.array([p[(nn >= s - 0.5) & (nn < s + 0.5)].mean() for s in shells])
+    nbar = np.array([nn[(nn >= s - 0.5) & (nn < s + 0.5)].mean() for s in shells])
+    return P, nbar
+
+
+def test_4_white_noise_power_spectrum():
+    # Sec. 3.4: modes below k_J grow and modes above it damp, P(k, t)/P(k, 0) ~ exp(2 gamma t)
+    # (64^3 x 32^3 FP32 cells, 34 GB)
+    print("test 4", flush=True)
+    w = inputs.white_noise_64_32()
+    f = _device_f(w, VP_F32)
+    sim = Simulator(config_of(w, VP_F32), f)
+    e0 = sim.energy()
+    nmax = 20
+    spectra = [_shell_power(sim.density().cpu().numpy(), nmax)[0]]
+    for _ in range(4):
+        sim.run(13, w.dt)
+        spectra.append(_shell_power(sim.density().cpu().numpy(), nmax)[0])
+        print("t", 13 * len(spectra[1:]) * w.dt, flush=True)
+    _, nbar = _shell_power(sim.density().cpu().numpy(), nmax)
+    e1 = sim.energy()
+    fmin = float(f.min())
+    sim.close()
+    del f
+    t = np.array([0.0, 0.2, 0.4, 0.6, 0.8])
+    P = np.array(spectra)
+    kk = nbar * 2 * math.pi / w.params["k_jeans"]
+    print("shell  k/kJ  2gamma  rate(0.2-0.6)  rate(0.4-0.8)  P(0.8)/P(0)")
+    for i in range(nmax):
+        g2 = 2 * gamma_of(kk[i]) if abs(kk[i] - 1) > 1e-3 else 0.0
+        r1 = np.polyfit(t[1:4], np.log(P[1:4, i]), 1)[0]
+        r2 = np.polyfit(t[2:5], np.log(P[2:5, i]), 1)[0]
+        print("%5d %6.3f %7.3f %9.3f %9.3f %10.3g" % (i + 1, kk[i], g2, r1, r2, P[4, i] / P[0, i]), flush=True)
+    print("mass drift", (e1[2] - e0[2]) / e0[2], "energy drift", (e1[3] - e0[3]) / abs(e0[3]), "fmin", fmin)
+    assert abs(e1[2] - e0[2]) / e0[2] < 1e-6
+    assert abs(e1[3] - e0[3]) / abs(e0[3]) < 1e-3
+    assert fmin >= 0.0
+    ratio = P[4] / P[0]
+    rate = np.array([np.polyfit(t[2:5], np.log(P[2:5, i]), 1)[0] for i in range(nmax)])
+    two_gamma = np.array([2 * gamma_of(k) for k in kk])
+    grow = kk < 0.8
+    assert np.all(ratio[grow] > 4.0)                        # unstable below k_J
+    assert np.all(ratio[kk > 1.1] < 0.3)                   # damped above it
+    # linear phase, t = 0.4 T .. 0.8 T, after the transient of a pure density perturbation
+    np.testing.assert_allclose(rate[grow], two_gamma[grow], rtol=0.05)
+    damp = (kk > 1.2) & (kk < 1.7)
+    np.testing.assert_allclose(rate[damp], two_gamma[damp], rtol=0.12)
+    # the damping of the shortest modes is slower than linear theory (Sec. 3.4)
+    assert np.all(rate[kk > 1.9] > two_gamma[kk > 1.9])
