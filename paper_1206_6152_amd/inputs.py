@@ -129,6 +129,50 @@ def king_48_48(W0: float = 6.0) -> Workload:
                     params=dict(W0=W0))
 
 
+def king_units(W0: float):
+    """(M, V, T) of one King sphere in units G = sigma = r0 = 1: its mass, V = r0/T and
+    T = (G M / r0^3)^(-1/2) (Sec. 3.5)."""
+    M = king_model(W0).mass * 9.0 / (4.0 * math.pi)
+    T = 1.0 / math.sqrt(M)
+    return M, 1.0 / T, T
+
+
+def king_w3_64x32() -> Workload:
+    """Test 5 (Sec. 3.5): King sphere W = 3 in units G = sigma = r0 = 1, box +-5.4 r0,
+    velocities +-1.5 V, 64^3 x 32^3 cells, isolated, to t = 1.2 T; the mass is
+    renormalised so that 2K/|U| = 1 on the grid."""
+    _, V, T = king_units(3.0)
+    return Workload(name="king_w3_64x32", n=(64,) * 3, nv=(32,) * 3, L=(10.8,) * 3,
+                    vmin=(-1.5 * V,) * 3, vmax=(1.5 * V,) * 3, G=1.0, bc=1, dt=0.0, steps=0,
+                    params=dict(W0=3.0, T=T, V=V, spheres=(((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),)))
+
+
+def king_merger_64x32() -> Workload:
+    """Test 6 (Sec. 3.6), Vlasov side: two W = 3 King spheres at (r0, r0, 0) and
+    (-r0, -r0, 0) moving at -0.2 V and +0.2 V along x, box +-6.4 r0, velocities +-2 V,
+    64^3 x 32^3 cells, isolated, to t = 5 T."""
+    _, V, T = king_units(3.0)
+    return Workload(name="king_merger_64x32", n=(64,) * 3, nv=(32,) * 3, L=(12.8,) * 3,
+                    vmin=(-2.0 * V,) * 3, vmax=(2.0 * V,) * 3, G=1.0, bc=1, dt=0.0, steps=0,
+                    params=dict(W0=3.0, T=T, V=V,
+                                spheres=(((1.0, 1.0, 0.0), (-0.2 * V, 0.0, 0.0)),
+                                         ((-1.0, -1.0, 0.0), (0.2 * V, 0.0, 0.0)))))
+
+
+def king_sphere_fields(w: Workload):
+    """Per sphere (centre, bulk velocity): Psi/sigma^2 at the spatial cell centres
+    (from the sphere's centre) and the cell-centre velocities relative to its bulk
+    velocity, for building f = sum of King distribution functions on the device."""
+    model = king_model(w.params["W0"])
+    X = np.meshgrid(*[w.xc(l) for l in range(3)], indexing="ij")
+    out = []
+    for c, u in w.params["spheres"]:
+        r = np.sqrt(sum((X[l] - c[l]) ** 2 for l in range(3)))
+        vrel = [w.vc(l) - u[l] for l in range(3)]
+        out.append((model.W_at(r), vrel))
+    return out
+
+
 WORKLOADS = {
     "landau_8x16": landau_8_16,
     "jeans_32x32": jeans_32_32,
@@ -136,6 +180,8 @@ WORKLOADS = {
     "slab_16x64x64_64": slab_16_64_64x64,
     "jeans_adjoint_16x24": jeans_adjoint_16_24,
     "white_noise_64x32": white_noise_64_32,
+    "king_w3_64x32": king_w3_64x32,
+    "king_merger_64x32": king_merger_64x32,
 }
 
 
