@@ -172,3 +172,41 @@ def test_full_size_step_properties(name, dtype):
     sim.close()
     del f
     torch.cuda.empty_cache()
+
+
+def test_jeans_fp32_error_budget_full_run():
+    # The benchmark workload (32^3 x 32^3, 50 steps) in FP32-stored f against the
+    # FP64-stored GPU path, which matches the oracle to 1e-12 (smaller grids, sampled
+    # full-size lines): the error of the FP32 form stated for f, density, potential
+    # and energy.
+    torch = _torch()
+    w = inputs.jeans_32_32()
+    res = {}
+    for dtype in (VP_F64, VP_F32):
+        f = device_f(w, dtype)
+        sim = Simulator(config_of(w, dtype), f)
+        e0 = sim.energy()
+        sim.run(w.steps, w.dt)
+        e1 = sim.energy()
+        rho = sim.density().cpu().numpy()
+        phi = sim.potential().cpu().numpy()
+        sim.close()
+        res[dtype] = (f.double(), e0, e1, rho, phi)
+        del f
+        torch.cuda.empty_cache()
+    f64, e0d, e1d, rho64, phi64 = res[VP_F64]
+    f32, e0s, e1s, rho32, phi32 = res[VP_F32]
+    err_f = float((f32 - f64).abs().sum() / f64.abs().sum())
+    del f32, f64, res
+    torch.cuda.empty_cache()
+    err_rho = float(np.abs(rho32 - rho64).max() / np.abs(rho64).max())
+    err_phi = float(np.abs(phi32 - phi64).max() / np.abs(phi64).max())
+    err_e = [abs(e1s[i] - e1d[i]) / abs(e1d[i]) for i in range(4)]
+    dmass = abs((e1s[2] - e0s[2]) - (e1d[2] - e0d[2])) / e0d[2]
+    print("FP32 vs FP64 after %d steps: f rel L1 %.2e, rho rel max %.2e, phi rel max %.2e, "
+          "K %.2e U %.2e M %.2e E %.2e, mass-drift difference %.2e" % (w.steps, err_f, err_rho, err_phi,
+                                                                        *err_e, dmass), flush=True)
+    assert err_f <= 1e-5
+    assert dmass <= 1e-6
+    assert err_rho <= 1e-5 and err_phi <= 1e-5
+    assert max(err_e) <= 1e-5
