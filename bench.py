@@ -167,7 +167,8 @@ def gpu_run(w, vp_dtype, steps, warmup):
     step_ms = wall * 1e3 / steps
     step_bytes = 19.0 * s * cells          # 9 sweeps x 2 + one density read
     # what a step of this build must move: every pass over f reads and writes it once
-    passes = sum(n for k, (ms, n) in phases.items() if k not in ("gravity",)) / max(1, steps)
+    passes = sum(n for k, (ms, n) in phases.items()
+                 if k not in ("gravity", "adjoint_sweep", "adjoint_gravity")) / max(1, steps)
     fused_bytes = passes * 2.0 * s * cells
     kname = kernel_name(dom, w, s)
     traffic = committed_traffic(w, s, kname)
@@ -202,6 +203,45 @@ def gpu_run(w, vp_dtype, steps, warmup):
         copy_GBps=copy_gbps,
         mass_drift=(e_end[2] - e_start[2]) / e_start[2],
     )
+
+
+def adjoint_run():
+    """The reverse mode (a8) on its own workload: vp_grad of L = -U after 40 FP32 steps of
+    16^3 x 24^3 cells, checkpoint every 8 steps (forward pass, segment recomputation,
+    reverse sweeps and reverse gravity), timed as one call after a warm-up call."""
+    import torch
+    from paper_1206_6152_amd import VP_F32, Simulator, config_of, inputs
+    w = inputs.jeans_adjoint_16_24()
+    k = w.params["ckpt"]
+    dev = torch.device("cuda:0")
+    f = build_f(w, torch.float32, dev)
+    f0 = f.clone()
+    sim = Simulator(config_of(w, VP_F32), f)
+    sim.grad(k, w.dt, k)                      # warm-up: first launches and work buffers
+    f.copy_(f0)
+    sim.accel()
+    torch.cuda.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    loss, g = sim.grad(w.steps, w.dt, k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = sim.profile_read()
+    sim.profile(False)
+    sim.close()
+    cells, s = w.cells, 4
+    del f, f0, g
+    torch.cuda.empty_cache()
+    ms, n = phases["adjoint_sweep"]
+    per = ms / n if n else 0.0
+    rev_bytes = 3.0 * s * cells               # read the forward input and lam, write lam
+    gbps = rev_bytes / (per * 1e-3) / 1e9 if per else 0.0
+    return dict(value=cells * w.steps / wall, unit="cell-updates/s (forward steps differentiated)",
+                workload=w.name, steps=w.steps, ckpt_every=k, ms_per_gradient=wall * 1e3, loss=loss,
+                roofline=dict(bound="hbm", kernel="reverse PFC sweep (sweep_adj_kernel)", achieved=gbps,
+                              peak=PEAK_HBM_GBPS, unit="GB/s", frac=gbps / PEAK_HBM_GBPS,
+                              algorithmic_bytes_per_launch=rev_bytes, avg_launch_ms=per, launches=n),
+                phases_ms={k_: v[0] for k_, v in phases.items() if v[1]})
 
 
 def cpu_baseline(w, seconds):
@@ -243,6 +283,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-stored run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
     ap.add_argument("--fp64-only", action="store_true",
                     help="profiling aid: run only the FP64-stored case (reported as the value, dtype f64)")
     args = ap.parse_args()
@@ -271,6 +312,9 @@ def main():
     if not args.no_fp64:
         r64 = gpu_run(w, VP_F64, args.steps, args.warmup)
         log("fp64", json.dumps(r64))
+    adj = None if args.no_adjoint else adjoint_run()
+    if adj:
+        log("adjoint", json.dumps(adj))
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
     if cpu:
         log("cpu", json.dumps(cpu))
@@ -303,6 +347,7 @@ def main():
         "phases_ms_per_launch": r32["phases_ms_per_launch"],
         "copy_GBps": r32["copy_GBps"],
         "cpu_baseline": cpu,
+        "adjoint": adj,
     }
     if r64:
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"],

@@ -163,9 +163,10 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * gravity solve (density, or the reduction of the T_x sums, Poisson,
  * acceleration), phase 7 the one-pass half
  * kick, phase 8 the one-pass pair of half kicks of vp_run, phase 9 the
- * one-pass T_y T_z. Arrays have VP_NPHASE entries and are caller-owned host
- * memory. */
-#define VP_NPHASE 10
+ * one-pass T_y T_z, phase 10 the reverse sweeps and phase 11 the reverse
+ * gravity map of vp_grad and vp_*_adjoint. Arrays have VP_NPHASE entries and
+ * are caller-owned host memory. */
+#define VP_NPHASE 12
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 
@@ -193,7 +194,7 @@ int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_
  * recomputes one segment at a time; writes dL/df0 to grad_f0_dev (device,
  * layout and type of f, caller-owned, 16-byte aligned) and L to *loss_host.
  * On return f holds the final state and the context its acceleration, as after
- * vp_run(nsteps, dt). Allocates about (nsteps/ckpt_every + ckpt_every + 11)
+ * vp_run(nsteps, dt). Allocates about (nsteps/ckpt_every + ckpt_every + 8)
  * copies of f for the call and frees them before returning (VP_ENOMEM if they
  * do not fit). Synchronises the stream. */
 int vp_sweep_adjoint(vp_ctx* ctx, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,

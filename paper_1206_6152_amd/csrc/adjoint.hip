@@ -25,95 +25,143 @@
 namespace vp {
 namespace {
 
-template <typename T, int N, bool REV>
-__device__ __forceinline__ T pfc_core_adj(const T (&v)[N], T (&lam)[N], T alpha, T c1, T c2, T dc1, T dc2,
-                                          bool periodic)
+// Reverse of pfc_line + store_shifted for one line; returns d<lam_out, out>/d nu.
+// `at(r)` is the offset of storage cell r of the lane's line from both bases.
+//
+// The view runs along the transport direction: view cell i is storage cell i
+// (nu >= 0) or N-1-i (nu < 0); the lane's forward line and lam line are
+// mirrored into the view with selects, so every lane follows the same
+// instruction stream whatever its sign. In the view the shift is
+// m = floor(|nu|) >= 0 and its transpose is lam_g_k = lam_out_{k+m} (zero
+// beyond an outflow end, wrapped if periodic). One pass over the cells in view
+// order then writes out_{i-1} once cell i is known: cell i sends its own terms
+// to out_i, its Lp interior-branch term to out_{i+1} and its Lm interior-branch
+// term to out_{i-1}.
+template <typename T, int N, typename AT>
+__device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at)
 {
 #pragma clang fp contract(off)
-#define AT(a, i) a[REV ? (N - 1 - (i)) : (i)]
+  const LineCoef<T> k = line_coef<T, N>(nu, periodic);
+  const bool neg = k.neg;
+  T w[N], l[N];
+#pragma unroll
+  for (int r = 0; r < N; r++) {
+    w[r] = fin[at(r)];
+    l[r] = lam[at(r)];
+  }
+  // f_inf and the first storage cell that holds it
   T finf = T(0);
   int am = -1;
 #pragma unroll
-  for (int i = 0; i < N; i++)
-    if (v[i] > finf) {
-      finf = v[i];
-      am = i;
+  for (int r = 0; r < N; r++)
+    if (w[r] > finf) {
+      finf = w[r];
+      am = r;
     }
-  const T twoinf = finf + finf;
-  T lg[N];
+  const int amv = (neg && am >= 0) ? N - 1 - am : am;   // its view index
 #pragma unroll
-  for (int i = 0; i < N; i++) lg[i] = lam[i];
-  T lfinf = T(0);
-  T lalpha = T(0);
-  T dm = periodic ? AT(v, 0) - AT(v, N - 1) : AT(v, 0);
-  const T ghost_r = periodic ? AT(v, 0) : T(0);
-#pragma unroll
-  for (int i = 0; i < N; i++) {
-    const T f0 = AT(v, i);
-    const T fr = (i + 1 < N) ? AT(v, i + 1 < N ? i + 1 : 0) : ghost_r;
-    const T dp = fr - f0;
-    const T h = f0 + f0;
-    const T r = twoinf - h;
-    const T lp = clamp_ordered(dp, -r, h);
-    const T lm = clamp_ordered(dm, -h, r);
-    // lam_F_i = lam_g_{i+1} - lam_g_i (the last face leaves the line unless periodic)
-    const T gnext = (i + 1 < N) ? AT(lg, i + 1 < N ? i + 1 : 0) : (periodic ? AT(lg, 0) : T(0));
-    const T lF = gnext - AT(lg, i);
-    const T inner = fma_(c2, lm, fma_(c1, lp, f0));
-    lalpha = lalpha + lF * (inner + alpha * (dc1 * lp + dc2 * lm));
-    const T lin = alpha * lF;
-    AT(lam, i) = AT(lam, i) + lin;
-    const T llp = c1 * lin;
-    const T llm = c2 * lin;
-    // Lp branch
-    if (dp < -r) {
-      AT(lam, i) = AT(lam, i) + T(2) * llp;
-      lfinf = lfinf - T(2) * llp;
-    } else if (dp > h) {
-      AT(lam, i) = AT(lam, i) + T(2) * llp;
-    } else {
-      if (i + 1 < N) AT(lam, i + 1 < N ? i + 1 : 0) = AT(lam, i + 1 < N ? i + 1 : 0) + llp;
-      else if (periodic) AT(lam, 0) = AT(lam, 0) + llp;
-      AT(lam, i) = AT(lam, i) - llp;
-    }
-    // Lm branch
-    if (dm < -h) {
-      AT(lam, i) = AT(lam, i) - T(2) * llm;
-    } else if (dm > r) {
-      lfinf = lfinf + T(2) * llm;
-      AT(lam, i) = AT(lam, i) - T(2) * llm;
-    } else {
-      AT(lam, i) = AT(lam, i) + llm;
-      if (i > 0) AT(lam, i > 0 ? i - 1 : 0) = AT(lam, i > 0 ? i - 1 : 0) - llm;
-      else if (periodic) AT(lam, N - 1) = AT(lam, N - 1) - llm;
-    }
-    dm = dp;
+  for (int i = 0; i < N / 2; i++) {
+    const T x = w[i], y = w[N - 1 - i];
+    w[i] = neg ? y : x;
+    w[N - 1 - i] = neg ? x : y;
+    const T p = l[i], q = l[N - 1 - i];
+    l[i] = neg ? q : p;
+    l[N - 1 - i] = neg ? p : q;
   }
+  const int m = neg ? -k.shift : k.shift;
+  if (m != 0) {
+    T g[N];
 #pragma unroll
-  for (int i = 0; i < N; i++)
-    if (i == am) lam[i] = lam[i] + lfinf;
-#undef AT
-  return lalpha;
-}
-
-// Reverse of pfc_line + apply_shift for one line; returns d<lam_out, out>/d nu.
-template <typename T, int N, typename ST, typename LD>
-__device__ __forceinline__ double pfc_line_adj(const T (&v)[N], T (&lam)[N], double nu, bool periodic, ST st,
-                                               LD ld)
-{
-  const LineCoef<T> k = line_coef<T, N>(nu, periodic);
-  const double alpha_d = (double)k.alpha;
-  (void)alpha_d;
-  // transpose of f'_i = g_{i-s}: lam_g_k = lam_out_{k+s}
-  apply_shift<T, N>(lam, -k.shift, periodic, st, ld);
+    for (int i = 0; i < N; i++) {
+      int src = i + m;
+      if (periodic) src %= N;
+      T x = T(0);
+#pragma unroll
+      for (int j = 0; j < N; j++)
+        if (j == src) x = l[j];
+      g[i] = x;
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++) l[i] = g[i];
+  }
   const double a = fabs(nu);
   const double al = a - floor(a);
   const T dc1 = (T)((2.0 * al - 3.0) / 6.0);
   const T dc2 = (T)(-al / 3.0);
-  T lalpha;
-  if (k.neg) lalpha = pfc_core_adj<T, N, true>(v, lam, k.alpha, k.c1, k.c2, dc1, dc2, periodic);
-  else lalpha = pfc_core_adj<T, N, false>(v, lam, k.alpha, k.c1, k.c2, dc1, dc2, periodic);
-  return k.neg ? -(double)lalpha : (double)lalpha;
+  const T alpha = k.alpha, c1 = k.c1, c2 = k.c2;
+  const T twoinf = finf + finf;
+  const T lg0 = l[0];
+  T dm = periodic ? w[0] - w[N - 1] : w[0];
+  // d<lam_out, out>/d alpha = sum_i lam_F_i d F_i / d alpha, first on its own
+  T lalpha = T(0);
+  {
+    T dmq = periodic ? w[0] - w[N - 1] : w[0];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      const T f0 = w[i];
+      const T fr = (i + 1 < N) ? w[i + 1 < N ? i + 1 : 0] : (periodic ? w[0] : T(0));
+      const T dp = fr - f0;
+      const T h = f0 + f0;
+      const T r = twoinf - h;
+      const T lp = clamp_ordered(dp, -r, h);
+      const T lm = clamp_ordered(dmq, -h, r);
+      const T lgn = (i + 1 < N) ? l[i + 1 < N ? i + 1 : 0] : (periodic ? lg0 : T(0));
+      const T lF = lgn - l[i];
+      const T q = fma_(c2, lm, fma_(c1, lp, f0));
+      lalpha = lalpha + lF * (q + alpha * (dc1 * lp + dc2 * lm));
+      dmq = dp;
+    }
+  }
+  // fresh copies, so that nothing of the first pass is kept for the second
+#pragma unroll
+  for (int i = 0; i < N; i++) asm volatile("" : "+v"(w[i]));
+  T lfinf = T(0);
+  T carry = T(0), pending = T(0), wrap_back = T(0);
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    const T f0 = w[i];
+    const T fr = (i + 1 < N) ? w[i + 1 < N ? i + 1 : 0] : (periodic ? w[0] : T(0));
+    const T dp = fr - f0;
+    const T h = f0 + f0;
+    const T r = twoinf - h;
+    const T lgi = l[i];
+    const T lgn = (i + 1 < N) ? l[i + 1 < N ? i + 1 : 0] : (periodic ? lg0 : T(0));
+    const T lF = lgn - lgi;                      // lam_F_i = lam_g_{i+1} - lam_g_i
+    const T lin = alpha * lF;
+    const T llp = c1 * lin;
+    const T llm = c2 * lin;
+    const bool p_lo = dp < -r, p_hi = dp > h;
+    const bool m_lo = dm < -h, m_hi = dm > r;
+    const bool p_mid = !(p_lo || p_hi), m_mid = !(m_lo || m_hi);
+    T own = lgi + lin;
+    own = own + (p_mid ? -llp : T(2) * llp);
+    own = own + (m_mid ? llm : -(T(2) * llm));
+    own = own + carry;
+    lfinf = lfinf - (p_lo ? T(2) * llp : T(0));
+    lfinf = lfinf + (m_hi ? T(2) * llm : T(0));
+    const T back = m_mid ? -llm : T(0);
+    if (i > 0) l[i > 0 ? i - 1 : 0] = pending + back;
+    else wrap_back = back;
+    pending = own;
+    carry = p_mid ? llp : T(0);
+    dm = dp;
+  }
+  l[N - 1] = pending + (periodic ? wrap_back : T(0));
+  if (periodic) l[0] = l[0] + carry;
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    if (i == amv) l[i] = l[i] + lfinf;
+  }
+  // back to storage order
+#pragma unroll
+  for (int i = 0; i < N / 2; i++) {
+    const T p = l[i], q = l[N - 1 - i];
+    l[i] = neg ? q : p;
+    l[N - 1 - i] = neg ? p : q;
+  }
+#pragma unroll
+  for (int r = 0; r < N; r++) lam[at(r)] = l[r];
+  return neg ? -(double)lalpha : (double)lalpha;
 }
 
 __device__ __forceinline__ double adj_line_nu(const SweepArgs& a, long long o, long long c)
@@ -123,27 +171,46 @@ __device__ __forceinline__ double adj_line_nu(const SweepArgs& a, long long o, l
   return (a.vmin + ((double)j + 0.5) * a.dv) * a.scale;
 }
 
-template <typename T, int N>
+// NARROW: the workgroup's first line is the uniform base and a lane's cells sit
+// at base + r*inner + off with a 32-bit offset (the host checks that they fit),
+// as in the forward strided sweep; otherwise 64-bit addressing per lane.
+template <typename T, int N, bool NARROW>
 __global__ __launch_bounds__(256) void sweep_adj_kernel(SweepArgs a, const T* fin, T* lam, double* dnu)
 {
   const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
   if (gid >= a.nlines) return;
-  const long long o = gid / a.inner;
-  const long long c = gid - o * a.inner;
-  const long long base = o * (long long)N * a.inner + c;
-  const long long inner = a.inner;
-  T v[N], l[N];
-#pragma unroll
-  for (int r = 0; r < N; r++) {
-    v[r] = fin[base + r * inner];
-    l[r] = lam[base + r * inner];
+  double d;
+  if constexpr (NARROW) {
+    const long long gid0 = (long long)blockIdx.x * 256;
+    const unsigned t = threadIdx.x;
+    const long long o0 = gid0 / a.inner;
+    const unsigned inner = (unsigned)a.inner;
+    const unsigned c0 = (unsigned)(gid0 - o0 * a.inner);
+    const unsigned cc = c0 + t;
+    const unsigned dov = cc / inner;
+    const unsigned c = cc - dov * inner;
+    const unsigned off = dov * (unsigned)(N * inner) + c - c0;
+    const long long b0 = o0 * N * (long long)inner + c0;
+    double nu;
+    if (a.velocity) {
+      const long long q0 = o0 / a.sp_div;
+      const unsigned r0 = (unsigned)(o0 - q0 * a.sp_div);
+      nu = a.accel[q0 + (r0 + dov) / (unsigned)a.sp_div] * a.scale;
+    } else {
+      const unsigned j = (c / (unsigned)a.j_div) % (unsigned)a.j_mod;
+      nu = (a.vmin + ((double)j + 0.5) * a.dv) * a.scale;
+    }
+    // uniform row base (r * inner) plus the lane's 32-bit offset
+    d = adj_line<T, N>(fin + b0, lam + b0, nu, a.periodic != 0,
+                       [&](int r) { return (long long)r * inner + off; });
+  } else {
+    const long long o = gid / a.inner;
+    const long long c = gid - o * a.inner;
+    const long long base = o * (long long)N * a.inner + c;
+    const long long inner = a.inner;
+    d = adj_line<T, N>(fin + base, lam + base, adj_line_nu(a, o, c), a.periodic != 0,
+                       [&](int r) { return (long long)r * inner; });
   }
-  T* p = lam + base;
-  const double d = pfc_line_adj<T, N>(v, l, adj_line_nu(a, o, c), a.periodic != 0,
-                                      [&](int r, T x) { p[(long long)r * inner] = x; },
-                                      [&](int r) { return p[(long long)r * inner]; });
-#pragma unroll
-  for (int r = 0; r < N; r++) p[(long long)r * inner] = l[r];
   if (dnu) dnu[gid] = d;
 }
 
@@ -170,8 +237,12 @@ hipError_t launch_adj_n(const SweepArgs& a, const void* fin, void* lam, double* 
 {
   if (a.nlines <= 0) return hipSuccess;
   const long long blocks = (a.nlines + 255) / 256;
-  hipLaunchKernelGGL((sweep_adj_kernel<T, N>), dim3((unsigned)blocks), dim3(256), 0, s, a,
-                     static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
+  if (narrow_ok(a, N))
+    hipLaunchKernelGGL((sweep_adj_kernel<T, N, true>), dim3((unsigned)blocks), dim3(256), 0, s, a,
+                       static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
+  else
+    hipLaunchKernelGGL((sweep_adj_kernel<T, N, false>), dim3((unsigned)blocks), dim3(256), 0, s, a,
+                       static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
   return hipGetLastError();
 }
 

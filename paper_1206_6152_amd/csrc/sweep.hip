@@ -53,13 +53,15 @@ __global__ __launch_bounds__(256) void sweep_strided_wide(SweepArgs a)
   if (gid >= a.nlines) return;
   const long long o = gid / a.inner;
   const long long c = gid - o * a.inner;
-  T* p = static_cast<T*>(a.f) + o * (long long)N * a.inner + c;
+  const long long base = o * (long long)N * a.inner + c;
+  const T* p = static_cast<const T*>(a.f) + base;
+  T* q = static_cast<T*>(a.out ? a.out : a.f) + base;
   const long long inner = a.inner;
   T v[N];
 #pragma unroll
   for (int r = 0; r < N; r++) v[r] = p[(long long)r * inner];
   const LineCoef<T> k = pfc_line<T, N>(v, line_nu_wide(a, o, c), a.periodic != 0);
-  store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { p[(long long)r * inner] = x; });
+  store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { q[(long long)r * inner] = x; });
 }
 
 // Strided lines, compact addressing: the workgroup's first line is the uniform
@@ -89,7 +91,9 @@ __global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
   const unsigned dov = cc / inner;          // slabs past the base line's slab
   const unsigned c = cc - dov * inner;
   const unsigned off = dov * (unsigned)(N * inner) + c - c0;
-  T* fb = static_cast<T*>(a.f) + (o0 * N * (long long)inner + c0);
+  const long long b0 = o0 * N * (long long)inner + c0;
+  const T* fb = static_cast<const T*>(a.f) + b0;
+  T* ob = static_cast<T*>(a.out ? a.out : a.f) + b0;
   double nu;
   if (a.velocity) {
     const long long sp_div = a.sp_div;
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
 #pragma unroll
   for (int r = 0; r < N; r++) v[r] = (fb + (long long)r * inner)[off];
   const LineCoef<T> k = pfc_line<T, N>(v, nu, a.periodic != 0);
-  store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { (fb + (long long)r * inner)[off] = x; });
+  store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { (ob + (long long)r * inner)[off] = x; });
   if constexpr (PART) {
     // every lane of the workgroup is live here (the host checks it)
     using PS = PartShape<T, N>;
@@ -166,7 +170,8 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
   const long long line0 = (long long)blockIdx.x * LINES;
   const long long left = a.nlines - line0;
   const int nl = left < LINES ? (int)left : LINES;
-  T* g = static_cast<T*>(a.f) + line0 * N;
+  const T* g = static_cast<const T*>(a.f) + line0 * N;
+  T* go = static_cast<T*>(a.out ? a.out : a.f) + line0 * N;
   if (nl == LINES) {
     if constexpr (VEC) {
       const VT* gv = reinterpret_cast<const VT*>(g);
@@ -213,7 +218,7 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
   __syncthreads();
   if (nl == LINES) {
     if constexpr (VEC) {
-      VT* gv = reinterpret_cast<VT*>(g);
+      VT* gv = reinterpret_cast<VT*>(go);
 #pragma unroll
       for (int k = 0; k < PER; k++) {
         const int e = (tid + k * LINES) * V;
@@ -227,12 +232,12 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
 #pragma unroll
       for (int k = 0; k < PER; k++) {
         const int e = tid + k * LINES;
-        g[e] = tile[(e / N) * P + (e % N)];
+        go[e] = tile[(e / N) * P + (e % N)];
       }
     }
   } else {
     const int count = nl * N;
-    for (int e = tid; e < count; e += LINES) g[e] = tile[(e / N) * P + (e % N)];
+    for (int e = tid; e < count; e += LINES) go[e] = tile[(e / N) * P + (e % N)];
   }
 }
 
@@ -420,16 +425,6 @@ hipError_t launch_drift_yz_sq(const DriftArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
-// compact addressing when every lane offset from its workgroup's first line
-// fits in 31 bits and the index arithmetic fits in 32 bits
-bool narrow_ok(const SweepArgs& a, int N)
-{
-  const bool no_straddle = (a.inner % 256) == 0;
-  const long long span = no_straddle ? 256 : (256 / a.inner + 2) * (long long)N * a.inner;
-  return a.inner < (1LL << 31) && span < (1LL << 31) && a.j_div < (1LL << 31) && a.j_mod < (1LL << 31) &&
-         a.sp_div < (1LL << 31);
-}
-
 template <typename T, int N>
 hipError_t launch_n(const SweepArgs& a, hipStream_t s)
 {
@@ -479,6 +474,16 @@ hipError_t launch_t(const SweepArgs& a, hipStream_t s)
 }
 
 }  // namespace
+
+// compact addressing when every lane offset from its workgroup's first line
+// fits in 31 bits and the index arithmetic fits in 32 bits
+bool narrow_ok(const SweepArgs& a, int N)
+{
+  const bool no_straddle = (a.inner % 256) == 0;
+  const long long span = no_straddle ? 256 : (256 / a.inner + 2) * (long long)N * a.inner;
+  return a.inner < (1LL << 31) && span < (1LL << 31) && a.j_div < (1LL << 31) && a.j_mod < (1LL << 31) &&
+         a.sp_div < (1LL << 31);
+}
 
 template <typename T>
 bool part_shape_ok(int n)

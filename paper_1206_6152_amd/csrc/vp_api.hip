@@ -286,6 +286,17 @@ int sweep(vp_ctx* c, int axis, double tau)
   return VP_OK;
 }
 
+// T_axis(tau) of the array at src, result written to dst (same layout, another array)
+int sweep_to(vp_ctx* c, int axis, double tau, const void* src, void* dst)
+{
+  vp::SweepArgs a = sweep_args(c, axis, tau);
+  a.f = const_cast<void*>(src);
+  a.out = dst;
+  PhaseScope scope(c, axis);
+  LAUNCH(c, vp::launch_sweep(a, c->cfg.dtype, c->stream));
+  return VP_OK;
+}
+
 // True when the x sweep can leave per-workgroup density sums: every
 // workgroup's 256 lines lie in one spatial (y, z) column.
 bool x_sweep_sums(vp_ctx* c)
@@ -308,6 +319,7 @@ int sweep_adjoint(vp_ctx* c, int axis, double tau, const void* fin, void* lam, d
     if (r) return r;
     c->dnu_len = a.nlines;
   }
+  PhaseScope scope(c, 10);
   LAUNCH(c, vp::launch_sweep_adjoint(a, c->cfg.dtype, fin, lam, want ? c->dnu : nullptr, c->stream));
   if (want) {
     const int l = axis - 3;
@@ -324,6 +336,7 @@ int accel_adjoint(vp_ctx* c, const double* lam_a, void* lam)
   int r;
   if (!c->lphi && (r = dalloc(&c->lphi, sizeof(double) * ext, "potential adjoint"))) return r;
   if (!c->radj && (r = dalloc(&c->radj, sizeof(double) * c->np, "density adjoint"))) return r;
+  PhaseScope scope(c, 11);
   LAUNCH(c, vp::launch_gradient_adj(c->lphi, lam_a, c->ng, c->dx[0], c->dx[1], c->dx[2], c->stream));
   if (c->cfg.bc == VP_BC_ISOLATED) {
     LAUNCH(c, vp::launch_load_ext(c->work, c->wg, c->lphi, c->ng, c->stream));
@@ -767,17 +780,19 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   const int nck = (nsteps + k - 1) / k;
   void* user_f = c->f;
   GradWork w{c};
-  std::vector<void*> ck(nck), stepb(k), sb(9);
-  void *W = nullptr, *fin = nullptr;
+  // ck: every k-th state of the forward run; st[1..k-1]: the other states of one
+  // segment, recomputed; in[1..8]: the inputs of sweeps 1..8 of one step
+  std::vector<void*> ck(nck), st(k, nullptr), in(9, nullptr);
+  void* fin = nullptr;
   double *ahist = nullptr, *lam_a = nullptr, *lam_p = nullptr;
   int r;
   for (int i = 0; i < nck; i++)
     if ((r = w.f(&ck[i], fb))) return r;
-  for (int i = 0; i < k; i++)
-    if ((r = w.f(&stepb[i], fb))) return r;
-  for (int i = 0; i < 9; i++)
-    if ((r = w.f(&sb[i], fb))) return r;
-  if ((r = w.f(&W, fb)) || (r = w.f(&fin, fb))) return r;
+  for (int i = 1; i < k; i++)
+    if ((r = w.f(&st[i], fb))) return r;
+  for (int i = 1; i < 9; i++)
+    if ((r = w.f(&in[i], fb))) return r;
+  if ((r = w.f(&fin, fb))) return r;
   if ((r = w.d(&ahist, ab * (size_t)(nsteps + 1))) || (r = w.d(&lam_a, ab)) || (r = w.d(&lam_p, ab))) return r;
   auto A = [&](int n) { return ahist + (size_t)n * 3 * c->np; };
   auto set_accel = [&](int n) { return copy_f(c, c->accel, A(n), ab); };
@@ -800,35 +815,33 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
 
   static const int axes[9] = {3, 4, 5, 2, 1, 0, 3, 4, 5};
-  c->f = W;
   for (int seg = nck - 1; seg >= 0 && r == VP_OK; seg--) {
     const int s0 = seg * k, s1 = (s0 + k < nsteps) ? s0 + k : nsteps;
-    if ((r = copy_f(c, W, ck[seg], fb))) break;
-    for (int n = s0; n < s1 && r == VP_OK; n++) {
-      if ((r = copy_f(c, stepb[n - s0], W, fb))) break;
-      if (n + 1 < s1) {
-        if ((r = set_accel(n))) break;
-        if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) break;
-      }
+    st[0] = ck[seg];
+    for (int n = s0; n + 1 < s1 && r == VP_OK; n++) {   // recompute the segment's states
+      if ((r = copy_f(c, st[n - s0 + 1], st[n - s0], fb)) || (r = set_accel(n))) break;
+      c->f = st[n - s0 + 1];
+      if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) break;
     }
+    c->f = user_f;
     for (int n = s1 - 1; n >= s0 && r == VP_OK; n--) {
-      // inputs of the nine sweeps of step n
-      if ((r = copy_f(c, W, stepb[n - s0], fb)) || (r = set_accel(n))) break;
-      for (int q = 0; q < 9 && r == VP_OK; q++) {
+      // inputs of the nine sweeps of step n, each sweep writing the next one's input
+      in[0] = st[n - s0];
+      if ((r = set_accel(n))) break;
+      for (int q = 0; q < 8 && r == VP_OK; q++) {
         if (q == 6 && (r = set_accel(n + 1))) break;
-        if ((r = copy_f(c, sb[q], W, fb))) break;
-        r = sweep(c, axes[q], q >= 3 && q < 6 ? dt : h);
+        r = sweep_to(c, axes[q], q >= 3 && q < 6 ? dt : h, in[q], in[q + 1]);
       }
-      if (r) break;
+      if (r) break;   // the stored acceleration is a_{n+1} from here
       // second half kick (acceleration a_{n+1}), then a_{n+1} = A(state after the drift)
       if ((r = copy_f(c, lam_a, lam_p, ab))) break;
-      for (int q = 8; q >= 6 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, sb[q], lam, lam_a);
+      for (int q = 8; q >= 6 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, in[q], lam, lam_a);
       if (r || (r = accel_adjoint(c, lam_a, lam))) break;
-      for (int q = 5; q >= 3 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], dt, sb[q], lam, nullptr);
+      for (int q = 5; q >= 3 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], dt, in[q], lam, nullptr);
       if (r) break;
       if ((r = set_accel(n))) break;
       HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
-      for (int q = 2; q >= 0 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, sb[q], lam, lam_p);
+      for (int q = 2; q >= 0 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, in[q], lam, lam_p);
     }
   }
   c->f = user_f;
@@ -853,10 +866,7 @@ int vp_grad(vp_ctx* c, int32_t nsteps, double dt, int32_t ckpt_every, void* grad
   if (ckpt_every < 1) return fail(VP_EINVAL, "ckpt_every must be >= 1");
   if (!grad_f0_dev || !loss_host) return fail(VP_EINVAL, "null pointer");
   if (reinterpret_cast<uintptr_t>(grad_f0_dev) % 16 != 0) return fail(VP_EINVAL, "gradient must be 16-byte aligned");
-  const bool prof = c->profiling;
-  c->profiling = false;
   r = grad_impl(c, nsteps, dt, ckpt_every, grad_f0_dev, loss_host);
-  c->profiling = prof;
   if (r) hipStreamSynchronize(c->stream);
   return r;
 }

@@ -26,10 +26,15 @@ struct SweepArgs {
   long long j_mod;
   double vmin, dv;     // cell-centre velocity v_j = vmin + (j + 1/2) dv
   double* part;        // optional: per-workgroup sums of the new line values (see below)
+  void* out;           // optional: write the result here (same layout) instead of over f
 };
 
 // Launch one sweep on the stream; dtype 0 = float, 1 = double.
 hipError_t launch_sweep(const SweepArgs& a, int dtype, hipStream_t s);
+
+// True when a workgroup of 256 consecutive lines of length N can be addressed
+// from its first line with 32-bit lane offsets (and 32-bit index arithmetic).
+bool narrow_ok(const SweepArgs& a, int N);
 
 // With part set, workgroup b (256 consecutive lines) also writes
 // part[b * n + r] = sum over its lines of the new value at cell r, in FP64.
