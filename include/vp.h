@@ -119,7 +119,8 @@ int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
  * exactly the corresponding vp_sweep calls in that order (same arithmetic, same
  * result bit for bit); vp_kick runs the three velocity sweeps of a spatial
  * cell in one pass over f when that cell's velocity block fits on chip
- * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3), and vp_drift runs
+ * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3; FP64 32^3 in two
+ * passes over half blocks, T_vx T_vy then T_vz), and vp_drift runs
  * T_z and T_y in one pass when a (y, z) plane of a slab of velocity cells
  * fits on chip (square 16^2, 24^2 or 32^2 planes), then T_x. */
 int vp_kick(vp_ctx* ctx, double tau);
@@ -164,9 +165,10 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * acceleration), phase 7 the one-pass half
  * kick, phase 8 the one-pass pair of half kicks of vp_run, phase 9 the
  * one-pass T_y T_z, phase 10 the reverse sweeps and phase 11 the reverse
- * gravity map of vp_grad and vp_*_adjoint. Arrays have VP_NPHASE entries and
- * are caller-owned host memory. */
-#define VP_NPHASE 12
+ * gravity map of vp_grad and vp_*_adjoint, phase 12 a pass of two velocity
+ * sweeps over half velocity blocks (blocks too large for one pass). Arrays
+ * have VP_NPHASE entries and are caller-owned host memory. */
+#define VP_NPHASE 13
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 

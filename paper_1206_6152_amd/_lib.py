@@ -34,9 +34,9 @@ EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential", "vp_energy",
            "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_accel_adjoint",
            "vp_grad", "vp_free", "vp_last_error"]
-VP_NPHASE = 12
+VP_NPHASE = 13
 PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity", "kick", "kick2", "drift_yz", "adjoint_sweep",
-          "adjoint_gravity"]
+          "adjoint_gravity", "kick_pair"]
 
 
 class VPError(RuntimeError):

@@ -353,6 +353,157 @@ hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
+// ---- two velocity sweeps in one pass over half a velocity block --------------
+// When a whole velocity block does not fit in LDS but half of it does (FP64
+// 32^3: 256 KiB, half 128 KiB), two consecutive sweeps whose lines both lie in
+// the half run in one pass: PASS 0 is T_vx then T_vy on the half with vz in
+// [c0, c0 + CH); PASS 1 is T_vz then T_vx on the half with vy in the chunk;
+// PASS 2 is T_vy then T_vz on the half with vx in the chunk. A half kick is
+// PASS 0 and a T_vz sweep; the two half kicks between two drifts (T_vx T_vy
+// T_vz T_vx T_vy T_vz) are PASS 0, 1, 2. Each LDS layout keeps the HBM-
+// contiguous axis contiguous and pads rows so both sweep directions are
+// bank-conflict free; the arithmetic is that of the single sweeps.
+template <typename T, int NV, int PASS>
+struct PairShape {
+  static constexpr int CH = NV / 2;
+  static constexpr int PAD = 64 / (int)sizeof(T);
+  static constexpr int SR = NV + 1;                       // padded vz row (PASS 1, 2)
+  // PASS 0: [vx][vy][c], vx stride SA; PASS 1: [vx][c][vz]; PASS 2: [c][vy][vz]
+  static constexpr int SA = NV * CH + PAD;
+  static constexpr int ELEMS = PASS == 0 ? NV * SA : NV * CH * SR;
+  static constexpr int BYTES = ELEMS * (int)sizeof(T);
+  static constexpr int THREADS = NV * CH;                  // lines per sweep
+  static constexpr int HALF = NV * NV * CH;
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && NV % 2 == 0;
+};
+
+template <typename T, int NV, int PASS>
+__device__ __forceinline__ void pair_coords(int e, int& gofs, int& lds)
+{
+  // element e of the half in HBM order -> offset in the block, LDS index
+  using S = PairShape<T, NV, PASS>;
+  if constexpr (PASS == 0) {          // runs of CH along vz
+    const int run = e / S::CH, c = e - run * S::CH;
+    gofs = run * NV + c;             // + c0 added by the caller
+    lds = (run / NV) * S::SA + (run % NV) * S::CH + c;
+  } else if constexpr (PASS == 1) {   // per vx, CH whole vz rows
+    const int vx = e / (S::CH * NV), rem = e - vx * (S::CH * NV);
+    const int c = rem / NV, vz = rem - c * NV;
+    gofs = vx * NV * NV + rem;       // + c0 * NV
+    lds = (vx * S::CH + c) * S::SR + vz;
+  } else {                            // CH whole vx planes
+    const int c = e / (NV * NV), rem = e - c * (NV * NV);
+    const int vy = rem / NV, vz = rem - vy * NV;
+    gofs = e;                         // + c0 * NV * NV
+    lds = (c * NV + vy) * S::SR + vz;
+  }
+}
+
+template <typename T, int NV, int PASS>
+__global__ __launch_bounds__((PairShape<T, NV, PASS>::THREADS)) void kick_pair_block(KickArgs a)
+{
+  using S = PairShape<T, NV, PASS>;
+  constexpr int CH = S::CH;
+  __shared__ T L[S::ELEMS];
+  const int tid = threadIdx.x;
+  const long long s = blockIdx.x >> 1;
+  const int c0 = (blockIdx.x & 1) * CH;
+  const long long cofs = PASS == 0 ? c0 : (PASS == 1 ? c0 * NV : c0 * NV * NV);
+  T* g = static_cast<T*>(a.f) + s * (long long)(NV * NV * NV) + cofs;
+  // 16-byte pieces: V consecutive values along vz, adjacent in HBM and in LDS;
+  // every load of the lane is issued before the first LDS write
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::n;
+  constexpr int PER = S::HALF / V / S::THREADS;
+  static_assert(S::HALF % (V * S::THREADS) == 0 && S::CH % V == 0, "half block is not whole 16-byte pieces");
+  {
+    VT x[PER];
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      int go, li;
+      pair_coords<T, NV, PASS>((tid + k * S::THREADS) * V, go, li);
+      x[k] = *reinterpret_cast<const VT*>(g + go);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      int go, li;
+      pair_coords<T, NV, PASS>((tid + k * S::THREADS) * V, go, li);
+#pragma unroll
+      for (int q = 0; q < V; q++) L[li + q] = lane_of<VT, T>(x[k], q);
+    }
+  }
+  __syncthreads();
+  // the two sweeps: axis A then axis B (0 = vx, 1 = vy, 2 = vz)
+  constexpr int AX0 = PASS == 0 ? 0 : (PASS == 1 ? 2 : 1);
+  constexpr int AX1 = PASS == 0 ? 1 : (PASS == 1 ? 0 : 2);
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const int ax = q == 0 ? AX0 : AX1;
+    const double nu = a.a[ax][s] * a.scale[ax];
+    int base, st;
+    if constexpr (PASS == 0) {
+      // lanes (other in-plane axis, c); vx stride SA, vy stride CH
+      const int o = tid / CH, c = tid - o * CH;
+      if (ax == 0) { base = o * CH + c; st = S::SA; }
+      else { base = o * S::SA + c; st = CH; }
+    } else if constexpr (PASS == 1) {
+      if (ax == 2) {                 // vz lines, lanes (vx, c)
+        const int vx = tid / CH, c = tid - vx * CH;
+        base = (vx * CH + c) * S::SR; st = 1;
+      } else {                       // vx lines, lanes (c, vz)
+        const int c = tid / NV, vz = tid - c * NV;
+        base = c * S::SR + vz; st = CH * S::SR;
+      }
+    } else {
+      if (ax == 1) {                 // vy lines, lanes (c, vz)
+        const int c = tid / NV, vz = tid - c * NV;
+        base = c * NV * S::SR + vz; st = S::SR;
+      } else {                       // vz lines, lanes (c, vy)
+        const int c = tid / NV, vy = tid - c * NV;
+        base = (c * NV + vy) * S::SR; st = 1;
+      }
+    }
+    T v[NV];
+#pragma unroll
+    for (int r = 0; r < NV; r++) v[r] = L[base + r * st];
+    const LineCoef<T> k = pfc_line<T, NV>(v, nu, false);
+    store_shifted<T, NV>(v, k.shift, false, [&](int r, T x) { L[base + r * st] = x; });
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    int go, li;
+    pair_coords<T, NV, PASS>((tid + k * S::THREADS) * V, go, li);
+    VT x;
+    T* xs = reinterpret_cast<T*>(&x);
+#pragma unroll
+    for (int q = 0; q < V; q++) xs[q] = L[li + q];
+    *reinterpret_cast<VT*>(g + go) = x;
+  }
+}
+
+template <typename T, int NV>
+hipError_t launch_kick_pair_cube(const KickArgs& a, int pass, hipStream_t s)
+{
+  if (a.np <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)(2 * a.np);
+  switch (pass) {
+    case 0:
+      static_assert(PairShape<T, NV, 0>::fits, "half block does not fit the LDS");
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 0>), dim3(blocks), dim3(PairShape<T, NV, 0>::THREADS), 0, s, a);
+      break;
+    case 1:
+      static_assert(PairShape<T, NV, 1>::fits, "half block does not fit the LDS");
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 1>), dim3(blocks), dim3(PairShape<T, NV, 1>::THREADS), 0, s, a);
+      break;
+    default:
+      static_assert(PairShape<T, NV, 2>::fits, "half block does not fit the LDS");
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 2>), dim3(blocks), dim3(PairShape<T, NV, 2>::THREADS), 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
 // ---- one-pass drift along z, then y -----------------------------------------
 // A workgroup takes one x index and W consecutive velocity cells of every
 // (y, z) cell (W contiguous values per (y, z) cell in HBM, one or more whole
@@ -564,6 +715,17 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
   }
   (void)w;
   return hipErrorInvalidValue;
+}
+
+bool kick_pair_supported(int dtype, const int nv[3])
+{
+  return dtype == 1 && nv[0] == 32 && nv[1] == 32 && nv[2] == 32;
+}
+
+hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)
+{
+  if (!kick_pair_supported(dtype, nv) || pass < 0 || pass > 2) return hipErrorInvalidValue;
+  return launch_kick_pair_cube<double, 32>(a, pass, s);
 }
 
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)

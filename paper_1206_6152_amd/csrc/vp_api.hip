@@ -376,6 +376,31 @@ int kick_n(vp_ctx* c, double tau, int reps)
     return VP_OK;
   }
   int r;
+  if (vp::kick_pair_supported(c->cfg.dtype, nv)) {
+    vp::KickArgs a{};
+    a.f = c->f;
+    a.np = c->np;
+    a.reps = 1;
+    for (int l = 0; l < 3; l++) {
+      a.a[l] = c->accel + (long long)l * c->np;
+      a.scale[l] = tau / c->dv[l];
+    }
+    if (reps == 2) {   // T_vx T_vy | T_vz T_vx | T_vy T_vz
+      for (int pass = 0; pass < 3; pass++) {
+        PhaseScope scope(c, 12);
+        LAUNCH(c, vp::launch_kick_pair(a, c->cfg.dtype, nv, pass, c->stream));
+      }
+      return VP_OK;
+    }
+    for (int i = 0; i < reps; i++) {
+      {
+        PhaseScope scope(c, 12);
+        LAUNCH(c, vp::launch_kick_pair(a, c->cfg.dtype, nv, 0, c->stream));
+      }
+      if ((r = sweep(c, 5, tau))) return r;
+    }
+    return VP_OK;
+  }
   for (int i = 0; i < reps; i++)
     if ((r = sweep(c, 3, tau)) || (r = sweep(c, 4, tau)) || (r = sweep(c, 5, tau))) return r;
   return VP_OK;

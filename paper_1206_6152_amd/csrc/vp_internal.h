@@ -59,6 +59,13 @@ struct KickArgs {
 bool kick_fused_supported(int dtype, const int nv[3]);
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
 
+// Two consecutive velocity sweeps in one pass over half velocity blocks (the
+// whole block does not fit on chip, half does): pass 0 = T_vy T_vx, pass 1 =
+// T_vx T_vz, pass 2 = T_vz T_vy (rightmost first). A half kick is pass 0 and a
+// T_vz sweep; two half kicks in a row are passes 0, 1, 2.
+bool kick_pair_supported(int dtype, const int nv[3]);
+hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
+
 // T_y T_z(tau) (z first) in one pass: tile = one x index x W velocity cells of
 // every (y, z) cell. Position sweeps: nu = v_l(j) tau / dx_l.
 struct DriftArgs {
