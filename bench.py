@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="profiling aid: run only the reverse-mode measurement and print it")
     ap.add_argument("--fp64-only", action="store_true",
                     help="profiling aid: run only the FP64-stored case (reported as the value, dtype f64)")
     args = ap.parse_args()
@@ -297,6 +299,9 @@ def main():
     w = inputs.WORKLOADS[args.workload]()
     log("workload", w.name, "cells", w.cells, "dt", w.dt)
 
+    if args.adjoint_only:
+        print(json.dumps(adjoint_run()), flush=True)
+        return
     if args.fp64_only:
         r64 = gpu_run(w, VP_F64, args.steps, args.warmup)
         print(json.dumps({"metric": METRIC, "value": r64["value"], "unit": "cell-updates/s", "n_gpus": 1,

@@ -214,6 +214,70 @@ __global__ __launch_bounds__(256) void sweep_adj_kernel(SweepArgs a, const T* fi
   if (dnu) dnu[gid] = d;
 }
 
+// Contiguous lines (inner == 1, the vz sweep): a workgroup stages LINES
+// consecutive lines of the forward input and of lam through LDS with coalesced
+// loads (rows padded to N + 1), each lane runs the reverse update of one line
+// there, and lam goes back the same way.
+template <typename T, int N>
+struct AdjContig {
+  static constexpr int P = N + 1;
+  static constexpr int LINES = (2 * 256 * P * (int)sizeof(T) <= 65536) ? 256
+                               : (2 * 128 * P * (int)sizeof(T) <= 65536) ? 128 : 64;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__((AdjContig<T, N>::LINES)) void sweep_adj_contig(SweepArgs a, const T* fin, T* lam,
+                                                                             double* dnu)
+{
+  using S = AdjContig<T, N>;
+  constexpr int LINES = S::LINES, P = S::P;
+  __shared__ T tf[LINES * P];
+  __shared__ T tl[LINES * P];
+  const int tid = threadIdx.x;
+  const long long line0 = (long long)blockIdx.x * LINES;
+  const long long left = a.nlines - line0;
+  const int nl = left < LINES ? (int)left : LINES;
+  const T* gf = fin + line0 * N;
+  T* gl = lam + line0 * N;
+  if (nl == LINES) {
+    T xf[N], xl[N];
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+      xf[k] = gf[tid + k * LINES];
+      xl[k] = gl[tid + k * LINES];
+    }
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+      const int e = tid + k * LINES;
+      tf[(e / N) * P + (e % N)] = xf[k];
+      tl[(e / N) * P + (e % N)] = xl[k];
+    }
+  } else {
+    for (int e = tid; e < nl * N; e += LINES) {
+      tf[(e / N) * P + (e % N)] = gf[e];
+      tl[(e / N) * P + (e % N)] = gl[e];
+    }
+  }
+  __syncthreads();
+  if (tid < nl) {
+    const long long line = line0 + tid;
+    const double nu = a.velocity ? a.accel[line / a.sp_div] * a.scale
+                                 : (a.vmin + 0.5 * a.dv) * a.scale;   // one velocity cell on this axis
+    const double d = adj_line<T, N>(tf + tid * P, tl + tid * P, nu, a.periodic != 0, [&](int r) { return r; });
+    if (dnu) dnu[line] = d;
+  }
+  __syncthreads();
+  if (nl == LINES) {
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+      const int e = tid + k * LINES;
+      gl[e] = tl[(e / N) * P + (e % N)];
+    }
+  } else {
+    for (int e = tid; e < nl * N; e += LINES) gl[e] = tl[(e / N) * P + (e % N)];
+  }
+}
+
 // lam_a[s] += scale * sum of dnu over the lines of spatial cell s (a
 // contiguous run of `per` line indices), fixed-order tree per workgroup.
 __global__ __launch_bounds__(256) void reduce_lines_kernel(double* lam_a, const double* dnu, long long per,
@@ -236,6 +300,12 @@ template <typename T, int N>
 hipError_t launch_adj_n(const SweepArgs& a, const void* fin, void* lam, double* dnu, hipStream_t s)
 {
   if (a.nlines <= 0) return hipSuccess;
+  if (a.inner == 1) {
+    constexpr int LINES = AdjContig<T, N>::LINES;
+    hipLaunchKernelGGL((sweep_adj_contig<T, N>), dim3((unsigned)((a.nlines + LINES - 1) / LINES)), dim3(LINES), 0, s,
+                       a, static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
+    return hipGetLastError();
+  }
   const long long blocks = (a.nlines + 255) / 256;
   if (narrow_ok(a, N))
     hipLaunchKernelGGL((sweep_adj_kernel<T, N, true>), dim3((unsigned)blocks), dim3(256), 0, s, a,
