@@ -138,6 +138,15 @@ int vp_set_accel(vp_ctx* ctx, const double* a_dev);
  * rho_dev ([Nx][Ny][Nz] FP64, device, caller-owned). Asynchronous. */
 int vp_density(vp_ctx* ctx, double* rho_dev);
 
+/* Velocity moment of an array a_dev with the layout and type of f, against
+ * weights w_dev ([Nvx][Nvy][Nvz] FP64, device): out_dev[s] = scale *
+ * sum_j a[s][j] w[j] for every spatial cell s ([Nx][Ny][Nz] FP64, device,
+ * caller-owned), accumulated in FP64 in a fixed order. With w = 1 and
+ * scale = dv^3 it is the density of Eq. (18); with w = M(v) and scale = rho0
+ * it carries a gradient dL/df0 of an initial condition f0 = rho0 (1 + delta(x))
+ * M(v) to dL/d delta(x). Asynchronous. */
+int vp_moment(vp_ctx* ctx, const void* a_dev, const double* w_dev, double scale, double* out_dev);
+
 /* Potential of the current f (Eqs. (18)-(21)) with one ghost layer, written to
  * phi_dev ([Nx+2][Ny+2][Nz+2] FP64, device, caller-owned). Periodic: the
  * k = 0 mode is zero and ghosts are periodic images. Isolated: ghosts hold

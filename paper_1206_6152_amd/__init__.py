@@ -13,12 +13,12 @@ from ._lib import (VP_BC_ISOLATED, VP_BC_PERIODIC, VP_F32, VP_F64, VPError, make
                    vp_accel, vp_config_validate, vp_density, vp_drift, vp_dt, vp_energy, vp_free, vp_kick,
                    vp_get_accel, vp_init, vp_last_error, vp_potential, vp_profile_enable,
                    vp_profile_read, vp_run, vp_set_accel, vp_step, vp_sweep, vp_sweep_adjoint,
-                   vp_accel_adjoint, vp_grad)
+                   vp_accel_adjoint, vp_grad, vp_moment)
 
 __all__ = ["Simulator", "VPError", "make_config", "config_of", "VP_F32", "VP_F64",
            "VP_BC_PERIODIC", "VP_BC_ISOLATED", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_kick", "vp_drift",
-           "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential",
+           "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_moment", "vp_potential",
            "vp_energy", "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint",
            "vp_accel_adjoint", "vp_grad", "vp_free",
            "vp_last_error", "vp_config_validate"]
@@ -89,6 +89,13 @@ class Simulator:
         rho = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
         vp_density(self.ctx, rho.data_ptr())
         return rho
+
+    def moment(self, a, w, scale: float = 1.0):
+        """scale * sum_v a(x, v) w(v) per spatial cell, FP64 (a like f, w of shape (Nvx, Nvy, Nvz))."""
+        w = w.to(device=self.device, dtype=self.torch.float64).contiguous()
+        out = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
+        vp_moment(self.ctx, a.data_ptr(), w.data_ptr(), scale, out.data_ptr())
+        return out
 
     def potential(self):
         phi = self.torch.empty(tuple(x + 2 for x in self.n), dtype=self.torch.float64, device=self.device)

@@ -31,7 +31,7 @@ ERROR_NAMES = {VP_EINVAL: "VP_EINVAL", VP_ENOMEM: "VP_ENOMEM", VP_EHIP: "VP_EHIP
 # every symbol include/vp.h declares
 EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_kick", "vp_drift",
-           "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_potential", "vp_energy",
+           "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_moment", "vp_potential", "vp_energy",
            "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_accel_adjoint",
            "vp_grad", "vp_free", "vp_last_error"]
 VP_NPHASE = 13
@@ -91,6 +91,7 @@ def lib():
             "vp_get_accel": [P, P],
             "vp_set_accel": [P, P],
             "vp_density": [P, P],
+            "vp_moment": [P, P, P, f64, P],
             "vp_potential": [P, P],
             "vp_energy": [P, D],
             "vp_dt": [P, f64, D],
@@ -180,6 +181,11 @@ def vp_set_accel(ctx: int, a_ptr: int) -> None:
 
 def vp_density(ctx: int, rho_ptr: int) -> None:
     check(lib().vp_density(ctx, ctypes.c_void_p(rho_ptr)))
+
+
+def vp_moment(ctx: int, a_ptr: int, w_ptr: int, scale: float, out_ptr: int) -> None:
+    check(lib().vp_moment(ctx, ctypes.c_void_p(a_ptr), ctypes.c_void_p(w_ptr), float(scale),
+                          ctypes.c_void_p(out_ptr)))
 
 
 def vp_potential(ctx: int, phi_ptr: int) -> None:

@@ -3,9 +3,10 @@
 FieldEnergy maps a per-cell initial density perturbation delta(x) to the field
 energy L = -U of the final state after a fixed number of steps, for the
 initial condition f0(x, v) = rho0 (1 + delta(x)) M(v). Forward and backward
-both run in libvp.so (the forward pass and the reverse sweeps); the only work
-done here is the chain rule through that initial-condition map,
-dL/d delta(x) = rho0 * sum_v M(v) dL/df0(x, v).
+both run in libvp.so: the forward pass and the reverse sweeps (vp_grad), and
+the chain rule through that initial-condition map,
+dL/d delta(x) = rho0 * sum_v M(v) dL/df0(x, v) (vp_moment). Forming f0 from
+delta is input preparation on the device.
 """
 from __future__ import annotations
 
@@ -27,18 +28,16 @@ class FieldEnergy(torch.autograd.Function):
         f = initial_f(delta, m_v, rho0, tdt)
         sim = Simulator(config_of(workload, vp_dtype), f)
         loss, g = sim.grad(nsteps, dt, ckpt_every)
+        # dL/d delta while the context is at hand (its f is no longer needed)
+        gd = sim.moment(g, m_v, rho0)
         sim.close()
-        ctx.save_for_backward(g, m_v)
-        ctx.rho0 = rho0
+        ctx.save_for_backward(gd)
         return torch.tensor(loss, dtype=torch.float64, device=delta.device)
 
     @staticmethod
     def backward(ctx, grad_out):
-        g, m_v = ctx.saved_tensors
-        np_ = g.shape[0] * g.shape[1] * g.shape[2]
-        gd = g.double().reshape(np_, -1) @ m_v.double().reshape(-1, 1)
-        gd = (ctx.rho0 * grad_out) * gd.reshape(g.shape[:3])
-        return gd, None, None, None, None, None, None, None
+        (gd,) = ctx.saved_tensors
+        return grad_out * gd, None, None, None, None, None, None, None
 
 
 def field_energy(delta, m_v, workload, vp_dtype, nsteps, dt, ckpt_every=8, rho0=1.0):

@@ -88,6 +88,27 @@ __global__ __launch_bounds__(RED) void density_kernel(const T* f, double* rho, l
   if (threadIdx.x == 0) rho[blockIdx.x] = s * dv3;
 }
 
+// out[s] = scale * sum_j a[s*nv3 + j] w[j] (FP64, fixed order per cell): one
+// workgroup per spatial cell, four accumulators per lane, then a tree.
+template <typename T>
+__global__ __launch_bounds__(RED) void weighted_moment_kernel(const T* a, const double* w, double* out,
+                                                              long long nv3, double scale)
+{
+  __shared__ double sh[RED];
+  const T* p = a + (long long)blockIdx.x * nv3;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  long long j = threadIdx.x;
+  for (; j + 3 * RED < nv3; j += 4 * RED) {
+    acc0 += (double)p[j] * w[j];
+    acc1 += (double)p[j + RED] * w[j + RED];
+    acc2 += (double)p[j + 2 * RED] * w[j + 2 * RED];
+    acc3 += (double)p[j + 3 * RED] * w[j + 3 * RED];
+  }
+  for (; j < nv3; j += RED) acc0 += (double)p[j] * w[j];
+  const double s = block_sum((acc0 + acc1) + (acc2 + acc3), sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s * scale;
+}
+
 // One thread per spatial cell (x, yz), x fastest so a wave reads whole rows of
 // the workgroup sums; the velocity chunks are added in their index order.
 __global__ __launch_bounds__(256) void density_from_parts_kernel(double* rho, const double* part, long long nyz,
@@ -530,6 +551,19 @@ hipError_t launch_density(const void* f, int dtype, double* rho, long long np, l
     hipLaunchKernelGGL(density_kernel<float>, dim3((unsigned)np), dim3(RED), 0, s, (const float*)f, rho, nv3, dv3);
   else
     hipLaunchKernelGGL(density_kernel<double>, dim3((unsigned)np), dim3(RED), 0, s, (const double*)f, rho, nv3, dv3);
+  return hipGetLastError();
+}
+
+hipError_t launch_weighted_moment(const void* a, int dtype, const double* w, double* out, long long np,
+                                  long long nv3, double scale, hipStream_t s)
+{
+  if (np <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(weighted_moment_kernel<float>, dim3((unsigned)np), dim3(RED), 0, s, (const float*)a, w, out,
+                       nv3, scale);
+  else
+    hipLaunchKernelGGL(weighted_moment_kernel<double>, dim3((unsigned)np), dim3(RED), 0, s, (const double*)a, w,
+                       out, nv3, scale);
   return hipGetLastError();
 }
 

@@ -690,6 +690,17 @@ int vp_density(vp_ctx* c, double* rho_dev)
   return VP_OK;
 }
 
+int vp_moment(vp_ctx* c, const void* a_dev, const double* w_dev, double scale, double* out_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!a_dev || !w_dev || !out_dev) return fail(VP_EINVAL, "null pointer");
+  if (!std::isfinite(scale)) return fail(VP_EINVAL, "scale must be finite");
+  LAUNCH(c, vp::launch_weighted_moment(a_dev, c->cfg.dtype, w_dev, out_dev, c->np, c->nv3, scale, c->stream));
+  return VP_OK;
+}
+
 int vp_potential(vp_ctx* c, double* phi_dev)
 {
   g_err.clear();

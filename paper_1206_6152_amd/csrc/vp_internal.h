@@ -86,6 +86,10 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s);
 hipError_t launch_density(const void* f, int dtype, double* rho, long long np, long long nv3,
                           double dv3, hipStream_t s);
 
+// out[s] = scale * sum_j a[s*nv3 + j] w[j]
+hipError_t launch_weighted_moment(const void* a, int dtype, const double* w, double* out, long long np,
+                                  long long nv3, double scale, hipStream_t s);
+
 // rho from the x sweep's workgroup sums: spatial column yz (of nyz) has
 // nchunk workgroups, each with n sums (one per x);
 // rho[x*nyz + yz] = dv3 * sum_k part[(yz*nchunk + k)*n + x], k in order.

@@ -121,3 +121,21 @@ def test_repeat_run_is_bitwise_deterministic():
         outs.append(f.cpu().numpy())
         sim.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
+def test_weighted_moment(dtype):
+    # vp_moment against the plain sum; with unit weights and dv^3 it is the density
+    w = small_workload(VP_BC_PERIODIC)
+    f0 = structured_f(w.shape, seed=12).astype(NP[dtype]).astype(np.float64)
+    sim, f = _sim(w, f0, dtype)
+    import torch
+    rng = np.random.default_rng(13)
+    wt = rng.standard_normal(w.nv)
+    out = sim.moment(f, torch.from_numpy(wt), 0.7).cpu().numpy()
+    ref = 0.7 * np.einsum("xyzabc,abc->xyz", f0, wt)
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+    dv3 = w.dv(0) * w.dv(1) * w.dv(2)
+    rho = sim.moment(f, torch.ones(w.nv, dtype=torch.float64), dv3).cpu().numpy()
+    np.testing.assert_allclose(rho, oracle.density(oracle_grid(w), f0), rtol=1e-13)
+    sim.close()
