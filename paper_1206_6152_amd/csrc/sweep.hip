@@ -505,13 +505,19 @@ hipError_t launch_kick_pair_cube(const KickArgs& a, int pass, hipStream_t s)
 }
 
 // ---- one-pass drift along z, then y -----------------------------------------
-// A workgroup takes one x index and W consecutive velocity cells of every
-// (y, z) cell (W contiguous values per (y, z) cell in HBM, one or more whole
-// cache lines). Each z line of that tile is read from HBM by one lane, updated
-// in registers and parked in LDS; after a barrier each y line is taken from
-// LDS by one lane, updated and written back to HBM. f crosses HBM once for the
-// two sweeps. Rows of W are unpadded; planes are padded to SY = W (mod 64)
-// elements so both sweep directions are bank-conflict free.
+// A tile is one x index and W consecutive velocity cells of every (y, z) cell
+// (W contiguous values per (y, z) cell in HBM, one or more whole cache lines).
+// Each z line of a tile is read from HBM by one lane, updated in registers and
+// parked in LDS; after a barrier each y line is taken from LDS by one lane,
+// updated and written back to HBM. f crosses HBM once for the two sweeps.
+// Rows of W are unpadded; planes are padded to SY = W (mod 64) elements so
+// both sweep directions are bank-conflict free.
+//
+// A workgroup takes TILES consecutive tiles. The z lines of the next tile are
+// loaded into registers while the current tile's y lines are swept and
+// stored, so that the single workgroup an LDS-sized tile leaves on a CU keeps
+// loads in flight while it computes. The tile loop is unrolled at compile
+// time, which keeps every memory-counter wait exact.
 template <typename T, int NY, int NZ, int W>
 struct DriftShape {
   static constexpr int SY0 = NZ * W;
@@ -523,56 +529,76 @@ struct DriftShape {
   static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && (W % (16 / (int)sizeof(T))) == 0;
 };
 
-template <typename T, int NY, int NZ, int W>
+template <typename T, int NY, int NZ, int W, int TILES>
 __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_block(DriftArgs a)
 {
   using S = DriftShape<T, NY, NZ, W>;
   __shared__ T L[S::ELEMS];
   const int tid = threadIdx.x;
   const long long nchunk = a.nv3 / W;
-  const long long ix = blockIdx.x / nchunk;
-  const long long jc = blockIdx.x - ix * nchunk;
-  T* f = static_cast<T*>(a.f) + ix * NY * NZ * a.nv3 + jc * W;   // (y, z, w) = f[(y*NZ + z)*nv3 + w]
+  const long long ntiles = a.nx * nchunk;
+  const long long t0 = (long long)blockIdx.x * TILES;
   const bool periodic = a.periodic != 0;
-  // z lines, lane (iy, w): straight from HBM (each row of a wave is whole
-  // cache lines), updated in registers, written into the LDS tile
+  // z-line lane (iy, w), y-line lane (iz, w)
+  const int iy = tid / W, wz = tid - iy * W;
+  const int iz = tid / W, wy = tid - iz * W;
+  auto tile_base = [&](long long t) {   // (y, z, w) = base[(y*NZ + z)*nv3 + w]
+    const long long ix = t / nchunk, jc = t - ix * nchunk;
+    return static_cast<T*>(a.f) + ix * NY * NZ * a.nv3 + jc * W;
+  };
+  // lane offsets within a tile are 32-bit (the host checks that a tile spans
+  // under 4 GiB); row pointers are uniform
+  const unsigned zoff = (unsigned)iy * (unsigned)(NZ * a.nv3) + (unsigned)wz;
+  const unsigned yoff = (unsigned)iz * (unsigned)a.nv3 + (unsigned)wy;
+  T v[NZ];
   if (tid < S::LZ) {
-    const int iy = tid / W, w = tid - iy * W;
-    const long long jz = (jc * W + w) % a.nvz;
-    const double nu = (a.vmin_z + ((double)jz + 0.5) * a.dv_z) * a.scale_z;
-    const T* src = f + (long long)iy * NZ * a.nv3 + w;
-    T v[NZ];
+    const T* src = tile_base(t0);
 #pragma unroll
-    for (int r = 0; r < NZ; r++) v[r] = src[(long long)r * a.nv3];
-    const int base = iy * S::SY + w;
-    const LineCoef<T> k = pfc_line<T, NZ>(v, nu, periodic);
-    store_shifted<T, NZ>(v, k.shift, periodic, [&](int r, T x) { L[base + r * W] = x; });
+    for (int r = 0; r < NZ; r++) v[r] = (src + (long long)r * a.nv3)[zoff];
   }
-  __syncthreads();
-  // y lines, lane (iz, w): from the LDS tile, updated in registers, written
-  // straight back to HBM
-  if (tid < S::LY) {
-    const int iz = tid / W, w = tid - iz * W;
-    const long long jy = ((jc * W + w) / a.nvz) % a.nvy;
-    const double nu = (a.vmin_y + ((double)jy + 0.5) * a.dv_y) * a.scale_y;
-    const int base = iz * W + w;
-    T v[NY];
 #pragma unroll
-    for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
-    const LineCoef<T> k = pfc_line<T, NY>(v, nu, periodic);
-    T* dst = f + (long long)iz * a.nv3 + w;
-    store_shifted<T, NY>(v, k.shift, periodic, [&](int r, T x) { dst[(long long)r * NZ * a.nv3] = x; });
+  for (int k = 0; k < TILES; k++) {
+    const long long t = t0 + k;
+    if (t >= ntiles) break;                       // uniform over the workgroup
+    const long long jc = t % nchunk;
+    if (tid < S::LZ) {
+      const long long jz = (jc * W + wz) % a.nvz;
+      const double nu = (a.vmin_z + ((double)jz + 0.5) * a.dv_z) * a.scale_z;
+      const int base = iy * S::SY + wz;
+      const LineCoef<T> c = pfc_line<T, NZ>(v, nu, periodic);
+      store_shifted<T, NZ>(v, c.shift, periodic, [&](int r, T x) { L[base + r * W] = x; });
+    }
+    __syncthreads();
+    // the next tile's z lines go into flight before this tile's y lines
+    if (k + 1 < TILES && t + 1 < ntiles && tid < S::LZ) {
+      const T* src = tile_base(t + 1);
+#pragma unroll
+      for (int r = 0; r < NZ; r++) v[r] = (src + (long long)r * a.nv3)[zoff];
+    }
+    if (tid < S::LY) {
+      const long long jy = ((jc * W + wy) / a.nvz) % a.nvy;
+      const double nu = (a.vmin_y + ((double)jy + 0.5) * a.dv_y) * a.scale_y;
+      const int base = iz * W + wy;
+      T u[NY];
+#pragma unroll
+      for (int r = 0; r < NY; r++) u[r] = L[base + r * S::SY];
+      const LineCoef<T> c = pfc_line<T, NY>(u, nu, periodic);
+      T* dst = tile_base(t);
+      store_shifted<T, NY>(u, c.shift, periodic, [&](int r, T x) { (dst + (long long)r * NZ * a.nv3)[yoff] = x; });
+    }
+    if (k + 1 < TILES) __syncthreads();           // LDS is reused by the next tile
   }
 }
 
-template <typename T, int NP, int W>
+template <typename T, int NP, int W, int TILES>
 hipError_t launch_drift_yz_sq(const DriftArgs& a, hipStream_t s)
 {
   using S = DriftShape<T, NP, NP, W>;
   static_assert(S::fits, "tile does not fit the LDS");
-  const long long blocks = a.nx * (a.nv3 / W);
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((drift_yz_block<T, NP, NP, W>), dim3((unsigned)blocks), dim3(S::THREADS), 0, s, a);
+  const long long tiles = a.nx * (a.nv3 / W);
+  if (tiles <= 0) return hipSuccess;
+  const long long blocks = (tiles + TILES - 1) / TILES;
+  hipLaunchKernelGGL((drift_yz_block<T, NP, NP, W, TILES>), dim3((unsigned)blocks), dim3(S::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -690,26 +716,29 @@ static int drift_yz_width(int dtype, int ny, int nz, long long nv3)
   if (dtype == 0) w = (ny == 16) ? 64 : (ny == 24 || ny == 32) ? 32 : 0;
   else w = (ny == 16) ? 32 : (ny == 24 || ny == 32) ? 16 : 0;
   if (w == 0 || nv3 % w != 0) return 0;
+  if ((long long)ny * nz * nv3 >= (1LL << 32)) return 0;   // 32-bit lane offsets within a tile
   return w;
 }
 
 bool drift_yz_supported(int dtype, int ny, int nz, long long nv3) { return drift_yz_width(dtype, ny, nz, nv3) != 0; }
 
+// Tiles per workgroup: four in FP32, two in FP64 (where the prefetched next
+// tile already doubles the register footprint of a line).
 hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
 {
   const int w = drift_yz_width(dtype, a.ny, a.nz, a.nv3);
   if (dtype == 0) {
     switch (a.ny) {
-      case 16: return launch_drift_yz_sq<float, 16, 64>(a, s);
-      case 24: return launch_drift_yz_sq<float, 24, 32>(a, s);
-      case 32: return launch_drift_yz_sq<float, 32, 32>(a, s);
+      case 16: return launch_drift_yz_sq<float, 16, 64, 4>(a, s);
+      case 24: return launch_drift_yz_sq<float, 24, 32, 4>(a, s);
+      case 32: return launch_drift_yz_sq<float, 32, 32, 4>(a, s);
       default: break;
     }
   } else {
     switch (a.ny) {
-      case 16: return launch_drift_yz_sq<double, 16, 32>(a, s);
-      case 24: return launch_drift_yz_sq<double, 24, 16>(a, s);
-      case 32: return launch_drift_yz_sq<double, 32, 16>(a, s);
+      case 16: return launch_drift_yz_sq<double, 16, 32, 2>(a, s);
+      case 24: return launch_drift_yz_sq<double, 24, 16, 2>(a, s);
+      case 32: return launch_drift_yz_sq<double, 32, 16, 2>(a, s);
       default: break;
     }
   }

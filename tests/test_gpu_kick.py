@@ -161,23 +161,28 @@ def test_run_equals_repeated_steps(shape, dtype):
     assert np.array_equal(outs[0][1], outs[1][1])
 
 
-@pytest.mark.parametrize("plane,nx", [(16, 48), (24, 32), (32, 12)])
-def test_one_pass_drift_many_tiles_per_workgroup(plane, nx):
-    # more (x, velocity chunk) tiles than workgroups resident at once: the
-    # FP32 drift walks several tiles per workgroup and prefetches the next one
-    print("case", plane, nx, flush=True)
-    w = small_workload(VP_BC_PERIODIC, n=(nx, plane, plane), nv=(8, 8, 16))
+@pytest.mark.parametrize("dtype,plane,nx,nv", [(VP_F32, 16, 48, (8, 8, 16)), (VP_F32, 24, 32, (8, 8, 16)),
+                                                (VP_F32, 32, 12, (8, 8, 16)), (VP_F32, 32, 3, (2, 3, 16)),
+                                                (VP_F32, 16, 1, (1, 3, 64)), (VP_F64, 32, 3, (1, 3, 16)),
+                                                (VP_F64, 24, 1, (1, 3, 16)), (VP_F64, 16, 3, (1, 3, 32))])
+def test_one_pass_drift_many_tiles_per_workgroup(dtype, plane, nx, nv):
+    # a workgroup walks several (x, velocity chunk) tiles (four in FP32, two
+    # in FP64) and loads the next one while it sweeps the current one; the
+    # tile counts here include ragged ends (9 and 3 tiles in FP32; 9, 3 and
+    # 9 in FP64)
+    print("case", dtype, plane, nx, nv, flush=True)
+    w = small_workload(VP_BC_PERIODIC, n=(nx, plane, plane), nv=nv)
     w = w.__class__(name="d", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
                     vmax=(1.5, 2.0, 1.5), G=1.0, bc=VP_BC_PERIODIC)
     rng = np.random.default_rng(plane + nx)
-    f0 = (structured_f(w.shape, seed=plane) + 1e-3 * rng.uniform(0, 1, w.shape)).astype(np.float32).astype(np.float64)
+    f0 = (structured_f(w.shape, seed=plane) + 1e-3 * rng.uniform(0, 1, w.shape)).astype(NP[dtype]).astype(np.float64)
     a = np.zeros((3,) + w.n)
     tau = 1.3 * 0.25 / 2.0
-    sim, f = _sim(w, f0, VP_F32, a)
+    sim, f = _sim(w, f0, dtype, a)
     sim.drift(tau)
     out = f.cpu().numpy()
     sim.close()
-    sim, f = _sim(w, f0, VP_F32, a)
+    sim, f = _sim(w, f0, dtype, a)
     for ax in (2, 1, 0):
         sim.sweep(ax, tau)
     split = f.cpu().numpy()
@@ -187,4 +192,4 @@ def test_one_pass_drift_many_tiles_per_workgroup(plane, nx):
     ref = f0
     for ax in (2, 1, 0):
         ref = oracle.sweep(g, ref, ax, tau)
-    assert rel_l1(out, ref) <= 2e-6
+    assert rel_l1(out, ref) <= (1e-14 if dtype == VP_F64 else 2e-6)
