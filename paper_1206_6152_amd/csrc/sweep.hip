@@ -34,6 +34,7 @@
 #include "vp_internal.h"
 
 #include "pfc_line.h"
+#include "buffer_io.h"
 
 namespace vp {
 namespace {
@@ -261,16 +262,14 @@ struct KickShape {
   static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && (NV3 % (16 / (int)sizeof(T))) == 0;
 };
 
-template <typename T, int NX, int NY, int NZ>
-__device__ __forceinline__ int kick_lds_index(int e)
-{
-  using S = KickShape<T, NX, NY, NZ>;
-  const int jz = e % NZ;
-  const int jy = (e / NZ) % NY;
-  const int jx = e / (NY * NZ);
-  return jx * S::SX + jy * S::SY + jz;
-}
-
+// Each velocity axis of a block is held in LDS in the orientation of its
+// sweep: reversed where the acceleration along it is negative, so every line
+// update transports toward increasing LDS index (the forward form of the
+// line update, with |nu|). The orientation enters only through addresses: the
+// row order of the first sweep's HBM loads (a scalar choice), each lane's LDS
+// base, and the order in which the block is read back out. One code path
+// serves all eight sign combinations, which keeps the register footprint that
+// of a single line update.
 template <typename T, int NX, int NY, int NZ, int REPS>
 __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_block(KickArgs a)
 {
@@ -279,63 +278,81 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
   constexpr int V = Vec16<T>::n;
   constexpr int NVEC = S::NV3 / V;
   constexpr int PER = (NVEC + S::THREADS - 1) / S::THREADS;
+  constexpr unsigned ROWB = NY * NZ * (unsigned)sizeof(T);   // bytes between vx rows
+  constexpr unsigned BLKB = S::NV3 * (unsigned)sizeof(T);
   __shared__ T L[S::ELEMS];
   const int tid = threadIdx.x;
   const long long s = blockIdx.x;
-  T* gs = static_cast<T*>(a.f) + s * S::NV3;
-  VT* g = reinterpret_cast<VT*>(gs);
-  const double nux = a.a[0][s] * a.scale[0];
-  const double nuy = a.a[1][s] * a.scale[1];
-  const double nuz = a.a[2][s] * a.scale[2];
-  // first vx sweep, lane (jy, jz): the line comes straight from HBM (a row of
-  // a wave is 64 consecutive values) and goes to LDS after the update
+  const auto rs = buf_rsrc(static_cast<const T*>(a.f) + s * S::NV3, BLKB);
+  const double nux = a.a[0][s] * a.scale[0], nuy = a.a[1][s] * a.scale[1], nuz = a.a[2][s] * a.scale[2];
+  const bool rx = nux < 0.0, ry = nuy < 0.0, rz = nuz < 0.0;
+  const LineCoef<T> cx = line_coef<T, NX>(fabs(nux), false);
+  const LineCoef<T> cy = line_coef<T, NY>(fabs(nuy), false);
+  const LineCoef<T> cz = line_coef<T, NZ>(fabs(nuz), false);
+  // first vx sweep, lane (jy, jz): the line comes from HBM (a row of a wave is
+  // 64 consecutive values) and goes to the lane's oriented (vy, vz) place
   if (tid < S::L0) {
-    const int base = (tid / NZ) * S::SY + (tid % NZ);
+    const int jy = tid / NZ, jz = tid - jy * NZ;
+    const int base = (ry ? NY - 1 - jy : jy) * S::SY + (rz ? NZ - 1 - jz : jz);
+    const unsigned voff = (unsigned)tid * (unsigned)sizeof(T);
     T v[NX];
 #pragma unroll
-    for (int r = 0; r < NX; r++) v[r] = gs[r * (NY * NZ) + tid];
-    const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
-    store_shifted<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
+    for (int r = 0; r < NX; r++) v[r] = buf_load<T>(rs, voff, (unsigned)(rx ? NX - 1 - r : r) * ROWB);
+    pfc_core<T, NX, false>(v, cx.alpha, cx.c1, cx.c2, false);
+    store_shifted<T, NX>(v, cx.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
   }
   __syncthreads();
+#pragma unroll
   for (int rep = 0; rep < REPS; rep++) {
-    if (rep > 0 && tid < S::L0) {  // vx lines: (jy, jz), from LDS on the second repetition
-      const int base = (tid / NZ) * S::SY + (tid % NZ);
-      T v[NX];
-  #pragma unroll
-      for (int r = 0; r < NX; r++) v[r] = L[base + r * S::SX];
-      const LineCoef<T> k = pfc_line<T, NX>(v, nux, false);
-      store_shifted<T, NX>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
+    if (rep > 0) {
+      if (tid < S::L0) {  // vx lines at LDS (vy, vz) = (tid / NZ, tid % NZ)
+        const int base = (tid / NZ) * S::SY + (tid % NZ);
+        T u[NX];
+#pragma unroll
+        for (int r = 0; r < NX; r++) u[r] = L[base + r * S::SX];
+        pfc_core<T, NX, false>(u, cx.alpha, cx.c1, cx.c2, false);
+        store_shifted<T, NX>(u, cx.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid < S::L1) {  // vy lines: (jx, jz)
+    if (tid < S::L1) {  // vy lines at LDS (vx, vz)
       const int base = (tid / NZ) * S::SX + (tid % NZ);
-      T v[NY];
-  #pragma unroll
-      for (int r = 0; r < NY; r++) v[r] = L[base + r * S::SY];
-      const LineCoef<T> k = pfc_line<T, NY>(v, nuy, false);
-      store_shifted<T, NY>(v, k.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; });
+      T u[NY];
+#pragma unroll
+      for (int r = 0; r < NY; r++) u[r] = L[base + r * S::SY];
+      pfc_core<T, NY, false>(u, cy.alpha, cy.c1, cy.c2, false);
+      store_shifted<T, NY>(u, cy.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; });
     }
     __syncthreads();
-    if (tid < S::L2) {  // vz lines: (jx, jy)
+    if (tid < S::L2) {  // vz lines at LDS (vx, vy)
       const int base = (tid / NY) * S::SX + (tid % NY) * S::SY;
-      T v[NZ];
-  #pragma unroll
-      for (int r = 0; r < NZ; r++) v[r] = L[base + r];
-      const LineCoef<T> k = pfc_line<T, NZ>(v, nuz, false);
-      store_shifted<T, NZ>(v, k.shift, false, [&](int r, T x) { L[base + r] = x; });
+      T u[NZ];
+#pragma unroll
+      for (int r = 0; r < NZ; r++) u[r] = L[base + r];
+      pfc_core<T, NZ, false>(u, cz.alpha, cz.c1, cz.c2, false);
+      store_shifted<T, NZ>(u, cz.shift, false, [&](int r, T x) { L[base + r] = x; });
     }
     __syncthreads();
   }
+  // back to HBM in storage order, 16 bytes per access
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int i = tid + k * S::THREADS;
     if (i < NVEC) {
+      const int e = i * V;
+      const int jz = e % NZ, jy = (e / NZ) % NY, jx = e / (NY * NZ);
+      const int row = (rx ? NX - 1 - jx : jx) * S::SX + (ry ? NY - 1 - jy : jy) * S::SY;
       VT x;
       T* xs = reinterpret_cast<T*>(&x);
+      if (rz) {
+        const int lo = row + (NZ - V - jz);          // cells jz .. jz+V-1 sit at lo+V-1 .. lo
 #pragma unroll
-      for (int q = 0; q < V; q++) xs[q] = L[kick_lds_index<T, NX, NY, NZ>(i * V + q)];
-      g[i] = x;
+        for (int q = 0; q < V; q++) xs[q] = L[lo + V - 1 - q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; q++) xs[q] = L[row + jz + q];
+      }
+      buf_store16(rs, (unsigned)i * 16u, 0u, x);
     }
   }
 }
@@ -345,6 +362,7 @@ hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
 {
   using S = KickShape<T, NV, NV, NV>;
   static_assert(S::fits, "velocity block does not fit the LDS");
+  static_assert(NV % Vec16<T>::n == 0, "16-byte output chunks stay inside a vz row");
   if (a.np <= 0) return hipSuccess;
   if (a.reps == 2)
     hipLaunchKernelGGL((kick_block<T, NV, NV, NV, 2>), dim3((unsigned)a.np), dim3(S::THREADS), 0, s, a);
