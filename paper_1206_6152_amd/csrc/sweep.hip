@@ -531,6 +531,11 @@ hipError_t launch_kick_pair_cube(const KickArgs& a, int pass, hipStream_t s)
 // Rows of W are unpadded; planes are padded to SY = W (mod 64) elements so
 // both sweep directions are bank-conflict free.
 //
+// Each line takes the forward form of the update with |nu|: a z line whose
+// vz is negative is mirrored in registers after its (storage-order) load and
+// parked in LDS in that order; the LDS rows are laid out in the orientation
+// of each column's y sweep, and a y line is stored back in storage order.
+//
 // A workgroup takes TILES consecutive tiles. The z lines of the next tile are
 // loaded into registers while the current tile's y lines are swept and
 // stored, so that the single workgroup an LDS-sized tile leaves on a CU keeps
@@ -567,7 +572,6 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
   // lane offsets within a tile are 32-bit (the host checks that a tile spans
   // under 4 GiB); row pointers are uniform
   const unsigned zoff = (unsigned)iy * (unsigned)(NZ * a.nv3) + (unsigned)wz;
-  const unsigned yoff = (unsigned)iz * (unsigned)a.nv3 + (unsigned)wy;
   T v[NZ];
   if (tid < S::LZ) {
     const T* src = tile_base(t0);
@@ -580,10 +584,23 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
     if (t >= ntiles) break;                       // uniform over the workgroup
     const long long jc = t % nchunk;
     if (tid < S::LZ) {
+      // the z line, mirrored where vz < 0, takes the forward update and is
+      // parked in LDS in that order, at its y place in the y sweep's
+      // orientation
       const long long jz = (jc * W + wz) % a.nvz;
+      const long long jy = ((jc * W + wz) / a.nvz) % a.nvy;
       const double nu = (a.vmin_z + ((double)jz + 0.5) * a.dv_z) * a.scale_z;
-      const int base = iy * S::SY + wz;
-      const LineCoef<T> c = pfc_line<T, NZ>(v, nu, periodic);
+      const bool rz = nu < 0.0;
+      const bool ry = (a.vmin_y + ((double)jy + 0.5) * a.dv_y) * a.scale_y < 0.0;
+      const int base = (ry ? NY - 1 - iy : iy) * S::SY + wz;
+#pragma unroll
+      for (int i = 0; i < NZ / 2; i++) {
+        const T x0 = v[i], x1 = v[NZ - 1 - i];
+        v[i] = rz ? x1 : x0;
+        v[NZ - 1 - i] = rz ? x0 : x1;
+      }
+      const LineCoef<T> c = line_coef<T, NZ>(fabs(nu), periodic);
+      pfc_core<T, NZ, false>(v, c.alpha, c.c1, c.c2, periodic);
       store_shifted<T, NZ>(v, c.shift, periodic, [&](int r, T x) { L[base + r * W] = x; });
     }
     __syncthreads();
@@ -594,15 +611,25 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
       for (int r = 0; r < NZ; r++) v[r] = (src + (long long)r * a.nv3)[zoff];
     }
     if (tid < S::LY) {
+      // lane (iz, w) takes storage z = iz (so each row a wave stores is whole
+      // cache lines), found at LDS z place iz, or NZ-1-iz where vz < 0; the
+      // y line comes out of LDS in its sweep orientation
+      const long long jz = (jc * W + wy) % a.nvz;
       const long long jy = ((jc * W + wy) / a.nvz) % a.nvy;
+      const bool rz = (a.vmin_z + ((double)jz + 0.5) * a.dv_z) * a.scale_z < 0.0;
       const double nu = (a.vmin_y + ((double)jy + 0.5) * a.dv_y) * a.scale_y;
-      const int base = iz * W + wy;
+      const bool ry = nu < 0.0;
+      const int base = (rz ? NZ - 1 - iz : iz) * W + wy;
       T u[NY];
 #pragma unroll
       for (int r = 0; r < NY; r++) u[r] = L[base + r * S::SY];
-      const LineCoef<T> c = pfc_line<T, NY>(u, nu, periodic);
+      const LineCoef<T> c = line_coef<T, NY>(fabs(nu), periodic);
+      pfc_core<T, NY, false>(u, c.alpha, c.c1, c.c2, periodic);
       T* dst = tile_base(t);
-      store_shifted<T, NY>(u, c.shift, periodic, [&](int r, T x) { (dst + (long long)r * NZ * a.nv3)[yoff] = x; });
+      const unsigned off = (unsigned)iz * (unsigned)a.nv3 + (unsigned)wy;
+      store_shifted<T, NY>(u, c.shift, periodic, [&](int r, T x) {
+        (dst + (long long)(ry ? NY - 1 - r : r) * NZ * a.nv3)[off] = x;
+      });
     }
     if (k + 1 < TILES) __syncthreads();           // LDS is reused by the next tile
   }
@@ -740,8 +767,8 @@ static int drift_yz_width(int dtype, int ny, int nz, long long nv3)
 
 bool drift_yz_supported(int dtype, int ny, int nz, long long nv3) { return drift_yz_width(dtype, ny, nz, nv3) != 0; }
 
-// Tiles per workgroup: four in FP32, two in FP64 (where the prefetched next
-// tile already doubles the register footprint of a line).
+// Tiles per workgroup: four, except two for the FP64 16- and 24-planes, whose
+// workgroups are small enough that several share a CU anyway.
 hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
 {
   const int w = drift_yz_width(dtype, a.ny, a.nz, a.nv3);
@@ -756,7 +783,7 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
     switch (a.ny) {
       case 16: return launch_drift_yz_sq<double, 16, 32, 2>(a, s);
       case 24: return launch_drift_yz_sq<double, 24, 16, 2>(a, s);
-      case 32: return launch_drift_yz_sq<double, 32, 16, 2>(a, s);
+      case 32: return launch_drift_yz_sq<double, 32, 16, 4>(a, s);
       default: break;
     }
   }

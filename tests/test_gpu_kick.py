@@ -166,9 +166,10 @@ def test_run_equals_repeated_steps(shape, dtype):
                                                 (VP_F32, 16, 1, (1, 3, 64)), (VP_F64, 32, 3, (1, 3, 16)),
                                                 (VP_F64, 24, 1, (1, 3, 16)), (VP_F64, 16, 3, (1, 3, 32))])
 def test_one_pass_drift_many_tiles_per_workgroup(dtype, plane, nx, nv):
-    # a workgroup walks several (x, velocity chunk) tiles (four in FP32, two
-    # in FP64) and loads the next one while it sweeps the current one; the
-    # tile counts here include ragged ends (9 and 3 tiles in FP32; 9, 3 and
+    # a workgroup walks several (x, velocity chunk) tiles (four, or two for
+    # FP64 planes of 16 and 24) and loads the next one while it sweeps the
+    # current one; the tile counts here include ragged ends (9 and 3 tiles in
+    # FP32; 9, 3 and
     # 9 in FP64)
     print("case", dtype, plane, nx, nv, flush=True)
     w = small_workload(VP_BC_PERIODIC, n=(nx, plane, plane), nv=nv)
