@@ -45,13 +45,18 @@ __device__ __forceinline__ void buf_store<double>(__amdgpu_buffer_rsrc_t r, unsi
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, x), r, voff, soff, 0);
 }
 
-// 16 bytes: four floats or two doubles
+// 16 bytes: four floats or two doubles. The whole offset is per lane and the
+// uniform offset field is the constant 0: with a register there, the
+// compiler's check for the hazard of a store wider than 8 bytes whose data
+// registers are rewritten right after issue does not fire on this target,
+// and an immediately following register write can replace data the store
+// has not yet read.
 template <typename VT>
-__device__ __forceinline__ void buf_store16(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const VT& x)
+__device__ __forceinline__ void buf_store16(__amdgpu_buffer_rsrc_t r, unsigned voff, const VT& x)
 {
   static_assert(sizeof(VT) == 16, "16-byte vector");
   using U4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0u, 0u, 0));
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, x), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, x), r, voff, 0u, 0);
 }
 
 }  // namespace

@@ -334,25 +334,36 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
     }
     __syncthreads();
   }
-  // back to HBM in storage order, 16 bytes per access
+  // back to HBM in storage order, 16 bytes per access. Lane t writes chunks
+  // t + k*THREADS; as THREADS = NY*NZ, all of a lane's chunks share their
+  // (vy, vz) cells and advance by V along vx, so the LDS place of chunk k is
+  // the lane's base plus k times a uniform step.
+  static_assert(S::THREADS == NY * NZ && NVEC == PER * S::THREADS, "whole chunks per lane");
+  const int e0 = tid * V;
+  const int jz = e0 % NZ, jy = (e0 / NZ) % NY, jx0 = e0 / (NY * NZ);
+  const int yz = (ry ? NY - 1 - jy : jy) * S::SY + (rz ? NZ - V - jz : jz);   // lowest LDS z place of the chunk
+  const int b0 = (rx ? NX - 1 - jx0 : jx0) * S::SX + yz;
+  const int step = (rx ? -V : V) * S::SX;
+  const unsigned vo = (unsigned)tid * 16u;
+  if (rz) {
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int i = tid + k * S::THREADS;
-    if (i < NVEC) {
-      const int e = i * V;
-      const int jz = e % NZ, jy = (e / NZ) % NY, jx = e / (NY * NZ);
-      const int row = (rx ? NX - 1 - jx : jx) * S::SX + (ry ? NY - 1 - jy : jy) * S::SY;
+    for (int k = 0; k < PER; k++) {
       VT x;
       T* xs = reinterpret_cast<T*>(&x);
-      if (rz) {
-        const int lo = row + (NZ - V - jz);          // cells jz .. jz+V-1 sit at lo+V-1 .. lo
+      const int lo = b0 + k * step;
 #pragma unroll
-        for (int q = 0; q < V; q++) xs[q] = L[lo + V - 1 - q];
-      } else {
+      for (int q = 0; q < V; q++) xs[q] = L[lo + V - 1 - q];
+      buf_store16(rs, vo + (unsigned)(k * S::THREADS) * 16u, x);
+    }
+  } else {
 #pragma unroll
-        for (int q = 0; q < V; q++) xs[q] = L[row + jz + q];
-      }
-      buf_store16(rs, (unsigned)i * 16u, 0u, x);
+    for (int k = 0; k < PER; k++) {
+      VT x;
+      T* xs = reinterpret_cast<T*>(&x);
+      const int lo = b0 + k * step;
+#pragma unroll
+      for (int q = 0; q < V; q++) xs[q] = L[lo + q];
+      buf_store16(rs, vo + (unsigned)(k * S::THREADS) * 16u, x);
     }
   }
 }
