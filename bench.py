@@ -124,7 +124,8 @@ def kernel_name(phase, w, elem_bytes):
         return "vp::kick_block<%s, %d, %d, %d, %d>" % (t, w.nv[0], w.nv[1], w.nv[2], 2 if phase == "kick2" else 1)
     if phase == "drift_yz":
         wd = {16: 64, 24: 32, 32: 32}[w.n[1]] if elem_bytes == 4 else {16: 32, 24: 16, 32: 16}[w.n[1]]
-        return "vp::drift_yz_block<%s, %d, %d, %d>" % (t, w.n[1], w.n[2], wd)
+        tiles = 4 if elem_bytes == 4 or w.n[1] == 32 else 2      # tiles per workgroup
+        return "vp::drift_yz_block<%s, %d, %d, %d, %d>" % (t, w.n[1], w.n[2], wd, tiles)
     axis = ["x", "y", "z", "vx", "vy", "vz"].index(phase)
     n = (list(w.n) + list(w.nv))[axis]
     if axis == 5:
