@@ -392,9 +392,10 @@ hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
 // T_vz T_vx T_vy T_vz) are PASS 0, 1, 2. Each LDS layout keeps the HBM-
 // contiguous axis contiguous and pads rows so both sweep directions are
 // bank-conflict free; the arithmetic is that of the single sweeps.
-template <typename T, int NV, int PASS>
+template <typename T, int NV, int PASS, int CH_ = NV / 2>
 struct PairShape {
-  static constexpr int CH = NV / 2;
+  static constexpr int CH = CH_;                         // planes across the third axis
+  static constexpr int NCH = NV / CH;                    // slices per velocity block
   static constexpr int PAD = 64 / (int)sizeof(T);
   static constexpr int SR = NV + 1;                       // padded vz row (PASS 1, 2)
   // PASS 0: [vx][vy][c], vx stride SA; PASS 1: [vx][c][vz]; PASS 2: [c][vy][vz]
@@ -402,15 +403,15 @@ struct PairShape {
   static constexpr int ELEMS = PASS == 0 ? NV * SA : NV * CH * SR;
   static constexpr int BYTES = ELEMS * (int)sizeof(T);
   static constexpr int THREADS = NV * CH;                  // lines per sweep
-  static constexpr int HALF = NV * NV * CH;
-  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && NV % 2 == 0;
+  static constexpr int HALF = NV * NV * CH;                // values in one slice
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && NV % CH == 0;
 };
 
-template <typename T, int NV, int PASS>
+template <typename T, int NV, int PASS, int CH_>
 __device__ __forceinline__ void pair_coords(int e, int& gofs, int& lds)
 {
-  // element e of the half in HBM order -> offset in the block, LDS index
-  using S = PairShape<T, NV, PASS>;
+  // element e of the slice in HBM order -> offset in the block, LDS index
+  using S = PairShape<T, NV, PASS, CH_>;
   if constexpr (PASS == 0) {          // runs of CH along vz
     const int run = e / S::CH, c = e - run * S::CH;
     gofs = run * NV + c;             // + c0 added by the caller
@@ -428,15 +429,15 @@ __device__ __forceinline__ void pair_coords(int e, int& gofs, int& lds)
   }
 }
 
-template <typename T, int NV, int PASS>
-__global__ __launch_bounds__((PairShape<T, NV, PASS>::THREADS)) void kick_pair_block(KickArgs a)
+template <typename T, int NV, int PASS, int CH_>
+__global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_pair_block(KickArgs a)
 {
-  using S = PairShape<T, NV, PASS>;
+  using S = PairShape<T, NV, PASS, CH_>;
   constexpr int CH = S::CH;
   __shared__ T L[S::ELEMS];
   const int tid = threadIdx.x;
-  const long long s = blockIdx.x >> 1;
-  const int c0 = (blockIdx.x & 1) * CH;
+  const long long s = blockIdx.x / S::NCH;
+  const int c0 = (int)(blockIdx.x - s * S::NCH) * CH;
   const long long cofs = PASS == 0 ? c0 : (PASS == 1 ? c0 * NV : c0 * NV * NV);
   T* g = static_cast<T*>(a.f) + s * (long long)(NV * NV * NV) + cofs;
   // 16-byte pieces: V consecutive values along vz, adjacent in HBM and in LDS;
@@ -450,13 +451,13 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS>::THREADS)) void kick_pair_b
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       int go, li;
-      pair_coords<T, NV, PASS>((tid + k * S::THREADS) * V, go, li);
+      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li);
       x[k] = *reinterpret_cast<const VT*>(g + go);
     }
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       int go, li;
-      pair_coords<T, NV, PASS>((tid + k * S::THREADS) * V, go, li);
+      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li);
 #pragma unroll
       for (int q = 0; q < V; q++) L[li + q] = lane_of<VT, T>(x[k], q);
     }
@@ -502,7 +503,7 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS>::THREADS)) void kick_pair_b
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     int go, li;
-    pair_coords<T, NV, PASS>((tid + k * S::THREADS) * V, go, li);
+    pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li);
     VT x;
     T* xs = reinterpret_cast<T*>(&x);
 #pragma unroll
@@ -519,17 +520,30 @@ hipError_t launch_kick_pair_cube(const KickArgs& a, int pass, hipStream_t s)
   switch (pass) {
     case 0:
       static_assert(PairShape<T, NV, 0>::fits, "half block does not fit the LDS");
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 0>), dim3(blocks), dim3(PairShape<T, NV, 0>::THREADS), 0, s, a);
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 0, NV / 2>), dim3(blocks), dim3(PairShape<T, NV, 0>::THREADS), 0, s, a);
       break;
     case 1:
       static_assert(PairShape<T, NV, 1>::fits, "half block does not fit the LDS");
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 1>), dim3(blocks), dim3(PairShape<T, NV, 1>::THREADS), 0, s, a);
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 1, NV / 2>), dim3(blocks), dim3(PairShape<T, NV, 1>::THREADS), 0, s, a);
       break;
     default:
       static_assert(PairShape<T, NV, 2>::fits, "half block does not fit the LDS");
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 2>), dim3(blocks), dim3(PairShape<T, NV, 2>::THREADS), 0, s, a);
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 2, NV / 2>), dim3(blocks), dim3(PairShape<T, NV, 2>::THREADS), 0, s, a);
       break;
   }
+  return hipGetLastError();
+}
+
+// T_vy then T_vz on slices of CH whole (vy, vz) planes (one slice per
+// workgroup): for velocity blocks too large for the half-block passes
+template <typename T, int NV, int CH>
+hipError_t launch_kick_planes(const KickArgs& a, hipStream_t s)
+{
+  using S = PairShape<T, NV, 2, CH>;
+  static_assert(S::fits, "slice does not fit the LDS");
+  if (a.np <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)(S::NCH * a.np);
+  hipLaunchKernelGGL((kick_pair_block<T, NV, 2, CH>), dim3(blocks), dim3(S::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -805,6 +819,17 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
 bool kick_pair_supported(int dtype, const int nv[3])
 {
   return dtype == 1 && nv[0] == 32 && nv[1] == 32 && nv[2] == 32;
+}
+
+bool kick_planes_supported(int dtype, const int nv[3])
+{
+  return dtype == 0 && nv[0] == 64 && nv[1] == 64 && nv[2] == 64;
+}
+
+hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)
+{
+  if (!kick_planes_supported(dtype, nv)) return hipErrorInvalidValue;
+  return launch_kick_planes<float, 64, 8>(a, s);
 }
 
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)

@@ -401,6 +401,22 @@ int kick_n(vp_ctx* c, double tau, int reps)
     }
     return VP_OK;
   }
+  if (vp::kick_planes_supported(c->cfg.dtype, nv)) {   // T_vx | T_vy T_vz per half kick
+    vp::KickArgs a{};
+    a.f = c->f;
+    a.np = c->np;
+    a.reps = 1;
+    for (int l = 0; l < 3; l++) {
+      a.a[l] = c->accel + (long long)l * c->np;
+      a.scale[l] = tau / c->dv[l];
+    }
+    for (int i = 0; i < reps; i++) {
+      if ((r = sweep(c, 3, tau))) return r;
+      PhaseScope scope(c, 12);
+      LAUNCH(c, vp::launch_kick_planes(a, c->cfg.dtype, nv, c->stream));
+    }
+    return VP_OK;
+  }
   for (int i = 0; i < reps; i++)
     if ((r = sweep(c, 3, tau)) || (r = sweep(c, 4, tau)) || (r = sweep(c, 5, tau))) return r;
   return VP_OK;

@@ -65,6 +65,11 @@ hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_
 // T_vz sweep; two half kicks in a row are passes 0, 1, 2.
 bool kick_pair_supported(int dtype, const int nv[3]);
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
+// T_vy then T_vz in one pass over slices of whole (vy, vz) planes, for
+// velocity blocks too large for the passes above (FP32 64^3: 8 planes, 130 KiB
+// per slice). A half kick is a T_vx sweep and this pass.
+bool kick_planes_supported(int dtype, const int nv[3]);
+hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
 
 // T_y T_z(tau) (z first) in one pass: tile = one x index x W velocity cells of
 // every (y, z) cell. Position sweeps: nu = v_l(j) tau / dx_l.
