@@ -45,10 +45,26 @@ def log(*a):
 
 
 def build_f(w, torch_dtype, device):
-    """f = (spatial factor) x (velocity factor), formed on the device in FP64 and
-    rounded once to the storage type, chunk by chunk."""
+    """f = (spatial factor) x (velocity factor), or the King distribution
+    rho1 (2 pi)^(-3/2) (exp(E) - 1) for E = Psi(x) - v^2/2 > 0 (isolated
+    workloads), formed on the device in FP64 and rounded once to the storage
+    type, chunk by chunk."""
+    import numpy as np
     import torch
     from paper_1206_6152_amd import inputs
+    if w.bc == 1:
+        psi = torch.from_numpy(inputs.king_psi(w).reshape(-1)).to(device)
+        V = np.meshgrid(*[w.vc(l) for l in range(3)], indexing="ij")
+        hv2 = torch.from_numpy((0.5 * (V[0] ** 2 + V[1] ** 2 + V[2] ** 2)).reshape(-1)).to(device)
+        pref = inputs.king_prefactor(w.params["W0"])
+        f = torch.empty(w.shape, dtype=torch_dtype, device=device)
+        fv = f.view(psi.numel(), hv2.numel())
+        chunk = max(1, (1 << 27) // hv2.numel())
+        for i in range(0, psi.numel(), chunk):
+            e = psi[i:i + chunk, None] - hv2[None, :]
+            fv[i:i + chunk] = torch.where(e > 0, pref * torch.expm1(e.clamp(min=0)), torch.zeros_like(e)).to(torch_dtype)
+        torch.cuda.synchronize()
+        return f
     dens, m = inputs.separable_factors(w)
     d = torch.from_numpy(dens.reshape(-1)).to(device)
     mv = torch.from_numpy(m.reshape(-1)).to(device)
@@ -112,10 +128,14 @@ PHASE_KERNEL = {
 
 
 def x_sweep_sums(w, elem_bytes):
-    """Whether the x sweep of a step also sums the density (256 velocity cells per
-    workgroup, x lines of 4..64 cells, 32 at most in FP64)."""
+    """Whether the x sweep of a step also sums the density: 256 velocity cells
+    per workgroup, and the workgroup's N x (256 + P) tile of new values (P the
+    largest power of two up to 64 with N P <= 256) within 68 KiB of LDS."""
     nv3 = w.nv[0] * w.nv[1] * w.nv[2]
-    return nv3 % 256 == 0 and w.n[0] in ((4, 8, 16, 32, 64) if elem_bytes == 4 else (4, 8, 16, 32))
+    n = w.n[0]
+    p = next(q for q in (64, 32, 16, 8, 4, 2, 1) if n * q <= 256) if n <= 256 else 0
+    return (nv3 % 256 == 0 and n in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128)
+            and n * (256 + p) * elem_bytes <= 68 * 1024)
 
 
 def kernel_name(phase, w, elem_bytes):
@@ -143,12 +163,15 @@ def gpu_run(w, vp_dtype, steps, warmup):
     copy_gbps = copy_bandwidth(f)
     sim = Simulator(config_of(w, vp_dtype), f)
     e_start = sim.energy()
-    sim.run(warmup, w.dt)
+    # a workload without a fixed step takes the Courant step (C = 0.5) of its
+    # initial state for every timed step
+    dt = w.dt if w.dt > 0 else sim.dt(0.5)
+    sim.run(warmup, dt)
     torch.cuda.synchronize()
     sim.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.run(steps, w.dt)
+    sim.run(steps, dt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     phases = sim.profile_read()

@@ -74,9 +74,13 @@ __global__ __launch_bounds__(256) void sweep_strided_wide(SweepArgs a)
 // over f.
 template <typename T, int N>
 struct PartShape {
-  static constexpr int ROW = 256 + 8;   // padded LDS row: the reads below hit distinct banks
-  static constexpr int P = 256 / N;      // lanes that share one row's sum
-  static constexpr bool ok = N >= 4 && N <= 64 && 256 % N == 0 && N * ROW * (int)sizeof(T) <= 68 * 1024;
+  // P lanes share one x row's sum: the largest power of two (at most 64)
+  // with N*P <= 256; each adds 256/P of the row's values in a fixed order,
+  // then the P partial sums meet in a butterfly
+  static constexpr int P = N * 64 <= 256 ? 64 : N * 32 <= 256 ? 32 : N * 16 <= 256 ? 16 :
+                           N * 8 <= 256 ? 8 : N * 4 <= 256 ? 4 : N * 2 <= 256 ? 2 : 1;
+  static constexpr int ROW = 256 + P;    // padded LDS row: the reads below hit distinct banks
+  static constexpr bool ok = N >= 1 && N <= 256 && N * ROW * (int)sizeof(T) <= 68 * 1024;
 };
 
 template <typename T, int N, bool PART>
@@ -117,12 +121,14 @@ __global__ __launch_bounds__(256) void sweep_strided(SweepArgs a)
     store_shifted<T, N>(v, k.shift, a.periodic != 0, [&](int r, T x) { tile[r * PS::ROW + t] = x; });
     __syncthreads();
     const int row = t / PS::P, q = t % PS::P;
-    double acc = 0.0;
+    if (row < N) {                    // N*P may be under 256: the other lanes idle
+      double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; j++) acc += (double)tile[row * PS::ROW + j * PS::P + q];
+      for (int j = 0; j < 256 / PS::P; j++) acc += (double)tile[row * PS::ROW + j * PS::P + q];
 #pragma unroll
-    for (int o = PS::P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (q == 0) a.part[(long long)blockIdx.x * N + row] = acc;
+      for (int o = PS::P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (q == 0) a.part[(long long)blockIdx.x * N + row] = acc;
+    }
   }
 }
 
@@ -736,11 +742,20 @@ template <typename T>
 bool part_shape_ok(int n)
 {
   switch (n) {
+    case 1: return PartShape<T, 1>::ok;
+    case 2: return PartShape<T, 2>::ok;
+    case 3: return PartShape<T, 3>::ok;
     case 4: return PartShape<T, 4>::ok;
+    case 6: return PartShape<T, 6>::ok;
     case 8: return PartShape<T, 8>::ok;
+    case 12: return PartShape<T, 12>::ok;
     case 16: return PartShape<T, 16>::ok;
+    case 24: return PartShape<T, 24>::ok;
     case 32: return PartShape<T, 32>::ok;
+    case 48: return PartShape<T, 48>::ok;
     case 64: return PartShape<T, 64>::ok;
+    case 96: return PartShape<T, 96>::ok;
+    case 128: return PartShape<T, 128>::ok;
     default: return false;
   }
 }
@@ -821,15 +836,16 @@ bool kick_pair_supported(int dtype, const int nv[3])
   return dtype == 1 && nv[0] == 32 && nv[1] == 32 && nv[2] == 32;
 }
 
+// FP32 48^3 (slices of 12 planes, 110 KiB) and 64^3 (8 planes, 130 KiB)
 bool kick_planes_supported(int dtype, const int nv[3])
 {
-  return dtype == 0 && nv[0] == 64 && nv[1] == 64 && nv[2] == 64;
+  return dtype == 0 && nv[0] == nv[1] && nv[1] == nv[2] && (nv[0] == 48 || nv[0] == 64);
 }
 
 hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)
 {
   if (!kick_planes_supported(dtype, nv)) return hipErrorInvalidValue;
-  return launch_kick_planes<float, 64, 8>(a, s);
+  return nv[0] == 48 ? launch_kick_planes<float, 48, 12>(a, s) : launch_kick_planes<float, 64, 8>(a, s);
 }
 
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)

@@ -1,8 +1,9 @@
 """The density of a step's Poisson solve comes from the x sweep's per-workgroup
-sums when the grid allows it (256 velocity cells per workgroup, x lines of 4
-to 64 cells). A step through the C ABI must then agree with the same step
-assembled from vp_kick, vp_drift, vp_accel (density from a separate pass over
-f) up to the summation order of rho, and with the oracle."""
+sums when the grid allows it (256 velocity cells per workgroup, and the
+workgroup's tile of new values within 68 KiB of LDS: x lines of up to 64
+cells in FP32, 32 in FP64). A step through the C ABI must then agree with the
+same step assembled from vp_kick, vp_drift, vp_accel (density from a separate
+pass over f) up to the summation order of rho, and with the oracle."""
 import numpy as np
 import pytest
 
@@ -20,8 +21,10 @@ def _workload(nx, bc, nv=(8, 8, 4)):
                            vmax=(1.5, 2.0, 1.5), G=2.0, bc=bc)
 
 
-@pytest.mark.parametrize("dtype,nx", [(VP_F32, 4), (VP_F32, 8), (VP_F32, 16), (VP_F32, 32), (VP_F32, 64),
-                                      (VP_F64, 4), (VP_F64, 16), (VP_F64, 32), (VP_F64, 64)])
+@pytest.mark.parametrize("dtype,nx", [(VP_F32, 3), (VP_F32, 4), (VP_F32, 8), (VP_F32, 12), (VP_F32, 16),
+                                      (VP_F32, 24), (VP_F32, 32), (VP_F32, 48), (VP_F32, 64), (VP_F32, 96),
+                                      (VP_F64, 4), (VP_F64, 6), (VP_F64, 16), (VP_F64, 24), (VP_F64, 32),
+                                      (VP_F64, 48), (VP_F64, 64)])
 @pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
 def test_step_density_from_x_sweep_sums(dtype, nx, bc):
     import torch

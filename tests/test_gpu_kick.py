@@ -30,8 +30,8 @@ def _accel(w, nu_max, tau, seed):
     return a
 
 
-CASES = [(VP_F32, 8), (VP_F32, 16), (VP_F32, 24), (VP_F32, 32), (VP_F32, 64), (VP_F64, 8), (VP_F64, 16),
-         (VP_F64, 24), (VP_F64, 32)]
+CASES = [(VP_F32, 8), (VP_F32, 16), (VP_F32, 24), (VP_F32, 32), (VP_F32, 48), (VP_F32, 64),
+         (VP_F64, 8), (VP_F64, 16), (VP_F64, 24), (VP_F64, 32)]
 
 
 @pytest.mark.parametrize("dtype,nv", CASES)
@@ -134,7 +134,8 @@ def test_one_pass_drift_planes(plane, dtype, nu_max, bc):
 
 @pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
 @pytest.mark.parametrize("shape", [((4, 16, 16), (16, 16, 16)), ((2, 6, 4), (8, 8, 8)), ((2, 3, 4), (8, 12, 16)),
-                                   ((2, 2, 4), (32, 32, 32)), ((2, 2, 2), (64, 64, 64))])
+                                   ((2, 2, 4), (32, 32, 32)), ((2, 2, 2), (48, 48, 48)),
+                                   ((2, 2, 2), (64, 64, 64))])
 def test_run_equals_repeated_steps(shape, dtype):
     # vp_run merges the closing and opening half kicks of consecutive steps;
     # the result must be the same bits as separate vp_step calls
