@@ -16,9 +16,11 @@
 // are, with f_inf the largest value of the line before the sweep,
 //   Lp_k = clamp(f_{k+1} - f_k, -2 (f_inf - f_k), 2 f_k),
 //   Lm_k = clamp(f_k - f_{k-1}, -2 f_k, 2 (f_inf - f_k)).
-// Transport toward decreasing index is the mirror image (the same update on the
-// reversed line; done by renaming registers, so it costs nothing and rounds
-// identically). Ghost cells are zero with zero flux (outflow) or periodic
+// Transport toward decreasing index is the mirror image: the same update on the
+// reversed line, which rounds identically. The plain sweeps reverse by renaming
+// registers (a wave whose lines all move one way) or with selects (a wave with
+// both signs); the one-pass kernels hold each axis in LDS in the orientation
+// of its sweep. Ghost cells are zero with zero flux (outflow) or periodic
 // images. Since f_k <= f_inf, the clamp bounds are always ordered, so each
 // clamp is one median-of-three.
 //
@@ -26,11 +28,13 @@
 // template parameter). Strided axes load the line straight from HBM: lanes of a
 // wave hold adjacent lines, so every row access of the wave is one contiguous
 // segment. Contiguous lines (the vz axis) are staged through LDS so that the
-// HBM traffic stays coalesced, then transposed into registers. A half kick can
-// instead keep a spatial cell's whole velocity block in LDS and run its three
-// sweeps in one pass over HBM. The alpha, c1, c2 of a line are computed in FP64
+// HBM traffic stays coalesced, then transposed into registers. Several sweeps
+// share one pass over HBM where their lines fit on chip together: a half kick
+// (or two in a row) on a whole velocity block, two velocity sweeps on half a
+// block or on slices of whole (vy, vz) planes, and T_z T_y on an x index times
+// a chunk of velocity cells. The alpha, c1, c2 of a line are computed in FP64
 // and rounded once to the storage type. The whole-cell part m of the shift is
-// applied through the line's own storage (LDS row or HBM line).
+// applied as the line is written out: each cell goes once to its shifted place.
 #include "vp_internal.h"
 
 #include "pfc_line.h"
@@ -250,8 +254,9 @@ __global__ __launch_bounds__((ContigShape<T, N>::lines)) void sweep_contig(Sweep
 
 // ---- one-pass half kick -----------------------------------------------------
 // The velocity block of one spatial cell (NX*NY*NZ values, contiguous in HBM)
-// is read once into LDS, swept along vx, then vy, then vz (each lane owns one
-// line per sweep, in registers), and written back once. The LDS layout pads
+// is read once (the vx lines straight into registers), swept along vx, then
+// vy, then vz in LDS (each lane owns one line per sweep, in registers), and
+// written back once. The LDS layout pads
 // each vz row to NZ+1 and each vx plane to SX = NZ (mod 64) elements, which
 // keeps the accesses of all three sweep directions on distinct banks.
 template <typename T, int NX, int NY, int NZ>
@@ -397,7 +402,9 @@ hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
 // PASS 0 and a T_vz sweep; the two half kicks between two drifts (T_vx T_vy
 // T_vz T_vx T_vy T_vz) are PASS 0, 1, 2. Each LDS layout keeps the HBM-
 // contiguous axis contiguous and pads rows so both sweep directions are
-// bank-conflict free; the arithmetic is that of the single sweeps.
+// bank-conflict free; the arithmetic is that of the single sweeps. With CH
+// below NV / 2 the same kernel takes slices of CH planes (PASS 2 only, for
+// blocks whose half does not fit either).
 template <typename T, int NV, int PASS, int CH_ = NV / 2>
 struct PairShape {
   static constexpr int CH = CH_;                         // planes across the third axis
