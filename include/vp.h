@@ -95,11 +95,10 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out);
  * T_vx, T_vy, T_vz at dt/2 with the new acceleration. The acceleration left in
  * the context serves the first half kick of the next step, so the Poisson
  * equation is solved once per step, after the position sweeps as the paper
- * states. When Nv^3 is a multiple of 256 and Nx is 4, 8, 16, 32 or 64 (64
- * only for VP_F32), the T_x sweep also sums its new values over velocity in
- * FP64 and the density of Eq. (18) comes from those sums (same value as
- * vp_density up to the order of the FP64 additions). dt must be finite and
- * > 0. */
+ * states. When Nv^3 is a multiple of 256 and Nx is at most 64 (VP_F32) or 32
+ * (VP_F64), the T_x sweep also sums its new values over velocity in FP64 and
+ * the density of Eq. (18) comes from those sums (same value as vp_density up
+ * to the order of the FP64 additions). dt must be finite and > 0. */
 int vp_step(vp_ctx* ctx, double dt);
 
 /* n consecutive vp_step calls with the same dt (n >= 0), with the same result
@@ -120,7 +119,9 @@ int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
  * result bit for bit); vp_kick runs the three velocity sweeps of a spatial
  * cell in one pass over f when that cell's velocity block fits on chip
  * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3; FP64 32^3 in two
- * passes over half blocks, T_vx T_vy then T_vz), and vp_drift runs
+ * passes over half blocks, T_vx T_vy then T_vz; FP32 48^3 and 64^3 as a T_vx
+ * sweep then T_vy T_vz in one pass over slices of whole (vy, vz) planes),
+ * and vp_drift runs
  * T_z and T_y in one pass when a (y, z) plane of a slab of velocity cells
  * fits on chip (square 16^2, 24^2 or 32^2 planes), then T_x. */
 int vp_kick(vp_ctx* ctx, double tau);
@@ -175,7 +176,8 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * kick, phase 8 the one-pass pair of half kicks of vp_run, phase 9 the
  * one-pass T_y T_z, phase 10 the reverse sweeps and phase 11 the reverse
  * gravity map of vp_grad and vp_*_adjoint, phase 12 a pass of two velocity
- * sweeps over half velocity blocks (blocks too large for one pass). Arrays
+ * sweeps over half velocity blocks or plane slices (blocks too large for one
+ * pass). Arrays
  * have VP_NPHASE entries and are caller-owned host memory. */
 #define VP_NPHASE 13
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
