@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP32 runs of the two full-size workloads of the paper's shapes")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="profiling aid: run only the reverse-mode measurement and print it")
     ap.add_argument("--fp64-only", action="store_true",
@@ -347,6 +349,20 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
     if cpu:
         log("cpu", json.dumps(cpu))
+    extra = None
+    if not args.no_extra and w.name == "jeans_32x32":
+        # one GPU's share of the 64^6 run and the isolated King sphere, FP32,
+        # 3 timed steps each (context, not the headline value)
+        extra = {}
+        for name in ("slab_16x64x64_64", "king_w6_48x48"):
+            wx = inputs.WORKLOADS[name]()
+            rx = gpu_run(wx, VP_F32, 3, 1)
+            extra[name] = {"cells": wx.cells, "ms_per_step": rx["ms_per_step"], "value": rx["value"],
+                           "unit": "cell-updates/s", "passes_per_step": rx["step_roofline"]["passes_per_step"],
+                           "fused_GBps": rx["step_roofline"]["fused_GBps"],
+                           "dominant": {k: rx["roofline"][k] for k in ("hip_kernel", "avg_launch_ms", "achieved",
+                                                                       "unit", "frac")}}
+            log("extra", name, json.dumps(extra[name]))
 
     out = {
         "metric": METRIC,
@@ -377,6 +393,7 @@ def main():
         "copy_GBps": r32["copy_GBps"],
         "cpu_baseline": cpu,
         "adjoint": adj,
+        "other_workloads": extra,
     }
     if r64:
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"],
