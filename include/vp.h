@@ -119,7 +119,7 @@ int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
  * result bit for bit); vp_kick runs the three velocity sweeps of a spatial
  * cell in one pass over f when that cell's velocity block fits on chip
  * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3; FP64 32^3 in two
- * passes over half blocks, T_vx T_vy then T_vz; FP32 48^3 and 64^3 as a T_vx
+ * passes over half blocks, T_vx T_vy then T_vz; 48^3 and 64^3 as a T_vx
  * sweep then T_vy T_vz in one pass over slices of whole (vy, vz) planes),
  * and vp_drift runs
  * T_z and T_y in one pass when a (y, z) plane of a slab of velocity cells

@@ -509,8 +509,20 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
     T v[NV];
 #pragma unroll
     for (int r = 0; r < NV; r++) v[r] = L[base + r * st];
-    const LineCoef<T> k = pfc_line<T, NV>(v, nu, false);
-    store_shifted<T, NV>(v, k.shift, false, [&](int r, T x) { L[base + r * st] = x; });
+    // one code path for both directions (nu is uniform over the block): the
+    // line is mirrored where nu < 0, takes the forward update with |nu|, and
+    // is written back through the mirrored index
+    const bool rev = nu < 0.0;
+#pragma unroll
+    for (int i = 0; i < NV / 2; i++) {
+      const T x0 = v[i], x1 = v[NV - 1 - i];
+      v[i] = rev ? x1 : x0;
+      v[NV - 1 - i] = rev ? x0 : x1;
+    }
+    const LineCoef<T> k = line_coef<T, NV>(fabs(nu), false);
+    pfc_core<T, NV, false>(v, k.alpha, k.c1, k.c2, false);
+    const int bw = rev ? base + (NV - 1) * st : base, sw = rev ? -st : st;
+    store_shifted<T, NV>(v, k.shift, false, [&](int r, T x) { L[bw + r * sw] = x; });
     __syncthreads();
   }
 #pragma unroll
@@ -843,16 +855,18 @@ bool kick_pair_supported(int dtype, const int nv[3])
   return dtype == 1 && nv[0] == 32 && nv[1] == 32 && nv[2] == 32;
 }
 
-// FP32 48^3 (slices of 12 planes, 110 KiB) and 64^3 (8 planes, 130 KiB)
+// 48^3 and 64^3 blocks: slices of 12 and 8 planes in FP32 (110 and 130
+// KiB), 6 and 4 in FP64 (110 and 130 KiB)
 bool kick_planes_supported(int dtype, const int nv[3])
 {
-  return dtype == 0 && nv[0] == nv[1] && nv[1] == nv[2] && (nv[0] == 48 || nv[0] == 64);
+  return (dtype == 0 || dtype == 1) && nv[0] == nv[1] && nv[1] == nv[2] && (nv[0] == 48 || nv[0] == 64);
 }
 
 hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)
 {
   if (!kick_planes_supported(dtype, nv)) return hipErrorInvalidValue;
-  return nv[0] == 48 ? launch_kick_planes<float, 48, 12>(a, s) : launch_kick_planes<float, 64, 8>(a, s);
+  if (dtype == 0) return nv[0] == 48 ? launch_kick_planes<float, 48, 12>(a, s) : launch_kick_planes<float, 64, 8>(a, s);
+  return nv[0] == 48 ? launch_kick_planes<double, 48, 6>(a, s) : launch_kick_planes<double, 64, 4>(a, s);
 }
 
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)

@@ -66,9 +66,9 @@ hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_
 bool kick_pair_supported(int dtype, const int nv[3]);
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
 // T_vy then T_vz in one pass over slices of whole (vy, vz) planes, for
-// velocity blocks too large for the passes above (FP32 48^3 and 64^3: 12 and
-// 8 planes, 110 and 130 KiB per slice). A half kick is a T_vx sweep and this
-// pass.
+// velocity blocks too large for the passes above (48^3 and 64^3: 12 and 8
+// planes in FP32, 6 and 4 in FP64, 110 and 130 KiB per slice). A half kick is
+// a T_vx sweep and this pass.
 bool kick_planes_supported(int dtype, const int nv[3]);
 hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
 

@@ -31,7 +31,7 @@ def _accel(w, nu_max, tau, seed):
 
 
 CASES = [(VP_F32, 8), (VP_F32, 16), (VP_F32, 24), (VP_F32, 32), (VP_F32, 48), (VP_F32, 64),
-         (VP_F64, 8), (VP_F64, 16), (VP_F64, 24), (VP_F64, 32)]
+         (VP_F64, 8), (VP_F64, 16), (VP_F64, 24), (VP_F64, 32), (VP_F64, 48), (VP_F64, 64)]
 
 
 @pytest.mark.parametrize("dtype,nv", CASES)
