@@ -48,18 +48,18 @@ __device__ __forceinline__ float fma_(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Fractional update g of one line held in registers, transport toward
-// increasing index of the view AT(i) = v[REV ? N-1-i : i]. Every rounding
+// increasing index. Every rounding
 // step is written out (automatic contraction is off), so all kernels that use
 // this routine produce the same bits:
 //   h = 2 f_k, r = 2 f_inf - h (= 2 (f_inf - f_k) exactly),
 //   Lp = med3(f_{k+1} - f_k, -r, h), Lm = med3(f_k - f_{k-1}, -h, r),
 //   q_k = fma(c2, Lm, fma(c1, Lp, f_k))   (the face flux is F_k = alpha q_k),
 //   g_k = fma(alpha, q_{k-1} - q_k, f_k)   (= f_k + F_{k-1} - F_k).
-template <typename T, int N, bool REV>
+template <typename T, int N>
 __device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool periodic)
 {
 #pragma clang fp contract(off)
-#define AT(i) v[REV ? (N - 1 - (i)) : (i)]
+#define AT(i) v[i]
   T finf = T(0);
 #pragma unroll
   for (int i = 0; i < N; i++) finf = max_(finf, v[i]);
@@ -95,34 +95,29 @@ __device__ __forceinline__ void pfc_core(T (&v)[N], T alpha, T c1, T c2, bool pe
 }
 
 // Fractional update of one line by Courant number nu; returns the coefficients
-// (whose shift the caller applies with apply_shift). A wave whose lines all
-// move the same way takes the matching register view; a wave with both signs
-// mirrors the negative lanes' data with selects around the forward update. All
-// routes do the same arithmetic in the same order and agree bit for bit.
+// (whose signed shift the caller applies, with store_shifted). A lane whose
+// line moves toward decreasing index mirrors its data with selects around the
+// forward update. One code path serves both directions: separate branches per
+// direction make the compiler hoist the work the branches share and keep both
+// sets of values alive, which costs far more registers than the two selects
+// per cell. Every route does the same arithmetic in the same order, so all
+// kernels agree bit for bit.
 template <typename T, int N>
 __device__ __forceinline__ LineCoef<T> pfc_line(T (&v)[N], double nu, bool periodic)
 {
   const LineCoef<T> k = line_coef<T, N>(nu, periodic);
-  const unsigned long long negs = __ballot(k.neg);
-  const unsigned long long live = __ballot(1);
-  if (negs == 0) {
-    pfc_core<T, N, false>(v, k.alpha, k.c1, k.c2, periodic);
-  } else if (negs == live) {
-    pfc_core<T, N, true>(v, k.alpha, k.c1, k.c2, periodic);
-  } else {
 #pragma unroll
-    for (int i = 0; i < N / 2; i++) {
-      const T x = v[i], y = v[N - 1 - i];
-      v[i] = k.neg ? y : x;
-      v[N - 1 - i] = k.neg ? x : y;
-    }
-    pfc_core<T, N, false>(v, k.alpha, k.c1, k.c2, periodic);
+  for (int i = 0; i < N / 2; i++) {
+    const T x = v[i], y = v[N - 1 - i];
+    v[i] = k.neg ? y : x;
+    v[N - 1 - i] = k.neg ? x : y;
+  }
+  pfc_core<T, N>(v, k.alpha, k.c1, k.c2, periodic);
 #pragma unroll
-    for (int i = 0; i < N / 2; i++) {
-      const T x = v[i], y = v[N - 1 - i];
-      v[i] = k.neg ? y : x;
-      v[N - 1 - i] = k.neg ? x : y;
-    }
+  for (int i = 0; i < N / 2; i++) {
+    const T x = v[i], y = v[N - 1 - i];
+    v[i] = k.neg ? y : x;
+    v[N - 1 - i] = k.neg ? x : y;
   }
   return k;
 }
@@ -158,25 +153,6 @@ __device__ __forceinline__ void store_shifted(const T (&v)[N], int shift, bool p
       const int src = i - shift;
       if (src < 0 || src >= N) st(i, T(0));
     }
-  }
-}
-
-// f'_i = g_{i-s}: the fractional result g goes to the line's storage, then
-// each cell reads its source (periodic wrap, or zero from beyond an outflow
-// boundary). st(r, x) / ld(r) access cell r of the lane's own line.
-template <typename T, int N, typename ST, typename LD>
-__device__ __forceinline__ void apply_shift(T (&v)[N], int shift, bool periodic, ST st, LD ld)
-{
-  if (shift == 0) return;
-#pragma unroll
-  for (int r = 0; r < N; r++) st(r, v[r]);
-  for (int r = 0; r < N; r++) {
-    int src = r - shift;
-    if (periodic) {
-      src %= N;
-      if (src < 0) src += N;
-    }
-    v[r] = (src >= 0 && src < N) ? ld(src) : T(0);
   }
 }
 

@@ -309,7 +309,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
     T v[NX];
 #pragma unroll
     for (int r = 0; r < NX; r++) v[r] = buf_load<T>(rs, voff, (unsigned)(rx ? NX - 1 - r : r) * ROWB);
-    pfc_core<T, NX, false>(v, cx.alpha, cx.c1, cx.c2, false);
+    pfc_core<T, NX>(v, cx.alpha, cx.c1, cx.c2, false);
     store_shifted<T, NX>(v, cx.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
   }
   __syncthreads();
@@ -321,7 +321,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
         T u[NX];
 #pragma unroll
         for (int r = 0; r < NX; r++) u[r] = L[base + r * S::SX];
-        pfc_core<T, NX, false>(u, cx.alpha, cx.c1, cx.c2, false);
+        pfc_core<T, NX>(u, cx.alpha, cx.c1, cx.c2, false);
         store_shifted<T, NX>(u, cx.shift, false, [&](int r, T x) { L[base + r * S::SX] = x; });
       }
       __syncthreads();
@@ -331,7 +331,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
       T u[NY];
 #pragma unroll
       for (int r = 0; r < NY; r++) u[r] = L[base + r * S::SY];
-      pfc_core<T, NY, false>(u, cy.alpha, cy.c1, cy.c2, false);
+      pfc_core<T, NY>(u, cy.alpha, cy.c1, cy.c2, false);
       store_shifted<T, NY>(u, cy.shift, false, [&](int r, T x) { L[base + r * S::SY] = x; });
     }
     __syncthreads();
@@ -340,7 +340,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
       T u[NZ];
 #pragma unroll
       for (int r = 0; r < NZ; r++) u[r] = L[base + r];
-      pfc_core<T, NZ, false>(u, cz.alpha, cz.c1, cz.c2, false);
+      pfc_core<T, NZ>(u, cz.alpha, cz.c1, cz.c2, false);
       store_shifted<T, NZ>(u, cz.shift, false, [&](int r, T x) { L[base + r] = x; });
     }
     __syncthreads();
@@ -520,7 +520,7 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
       v[NV - 1 - i] = rev ? x0 : x1;
     }
     const LineCoef<T> k = line_coef<T, NV>(fabs(nu), false);
-    pfc_core<T, NV, false>(v, k.alpha, k.c1, k.c2, false);
+    pfc_core<T, NV>(v, k.alpha, k.c1, k.c2, false);
     const int bw = rev ? base + (NV - 1) * st : base, sw = rev ? -st : st;
     store_shifted<T, NV>(v, k.shift, false, [&](int r, T x) { L[bw + r * sw] = x; });
     __syncthreads();
@@ -650,7 +650,7 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
         v[NZ - 1 - i] = rz ? x0 : x1;
       }
       const LineCoef<T> c = line_coef<T, NZ>(fabs(nu), periodic);
-      pfc_core<T, NZ, false>(v, c.alpha, c.c1, c.c2, periodic);
+      pfc_core<T, NZ>(v, c.alpha, c.c1, c.c2, periodic);
       store_shifted<T, NZ>(v, c.shift, periodic, [&](int r, T x) { L[base + r * W] = x; });
     }
     __syncthreads();
@@ -674,7 +674,7 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
 #pragma unroll
       for (int r = 0; r < NY; r++) u[r] = L[base + r * S::SY];
       const LineCoef<T> c = line_coef<T, NY>(fabs(nu), periodic);
-      pfc_core<T, NY, false>(u, c.alpha, c.c1, c.c2, periodic);
+      pfc_core<T, NY>(u, c.alpha, c.c1, c.c2, periodic);
       T* dst = tile_base(t);
       const unsigned off = (unsigned)iz * (unsigned)a.nv3 + (unsigned)wy;
       store_shifted<T, NY>(u, c.shift, periodic, [&](int r, T x) {
