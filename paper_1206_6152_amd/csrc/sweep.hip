@@ -345,10 +345,10 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
     }
     __syncthreads();
   }
-  // back to HBM in storage order, 16 bytes per access. Lane t writes chunks
-  // t + k*THREADS; as THREADS = NY*NZ, all of a lane's chunks share their
-  // (vy, vz) cells and advance by V along vx, so the LDS place of chunk k is
-  // the lane's base plus k times a uniform step.
+  // back to HBM (over f, or to out) in storage order, 16 bytes per access.
+  // Lane t writes chunks t + k*THREADS; as THREADS = NY*NZ, all of a lane's
+  // chunks share their (vy, vz) cells and advance by V along vx, so the LDS
+  // place of chunk k is the lane's base plus k times a uniform step.
   static_assert(S::THREADS == NY * NZ && NVEC == PER * S::THREADS, "whole chunks per lane");
   const int e0 = tid * V;
   const int jz = e0 % NZ, jy = (e0 / NZ) % NY, jx0 = e0 / (NY * NZ);
@@ -356,6 +356,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
   const int b0 = (rx ? NX - 1 - jx0 : jx0) * S::SX + yz;
   const int step = (rx ? -V : V) * S::SX;
   const unsigned vo = (unsigned)tid * 16u;
+  const auto ws = a.out ? buf_rsrc(static_cast<const T*>(a.out) + s * S::NV3, BLKB) : rs;
   if (rz) {
 #pragma unroll
     for (int k = 0; k < PER; k++) {
@@ -364,7 +365,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
       const int lo = b0 + k * step;
 #pragma unroll
       for (int q = 0; q < V; q++) xs[q] = L[lo + V - 1 - q];
-      buf_store16(rs, vo + (unsigned)(k * S::THREADS) * 16u, x);
+      buf_store16(ws, vo + (unsigned)(k * S::THREADS) * 16u, x);
     }
   } else {
 #pragma unroll
@@ -374,7 +375,7 @@ __global__ __launch_bounds__((KickShape<T, NX, NY, NZ>::THREADS)) void kick_bloc
       const int lo = b0 + k * step;
 #pragma unroll
       for (int q = 0; q < V; q++) xs[q] = L[lo + q];
-      buf_store16(rs, vo + (unsigned)(k * S::THREADS) * 16u, x);
+      buf_store16(ws, vo + (unsigned)(k * S::THREADS) * 16u, x);
     }
   }
 }

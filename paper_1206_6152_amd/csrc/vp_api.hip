@@ -824,6 +824,33 @@ int copy_f(vp_ctx* c, void* dst, const void* src, size_t bytes)
   return VP_OK;
 }
 
+// dst = T_vz T_vy T_vx(tau) src (dst may not alias src): one pass when the
+// velocity block fits on chip, else a copy and the kick in place. c->f is
+// left pointing at dst.
+int kick_to(vp_ctx* c, double tau, const void* src, void* dst, size_t fbytes)
+{
+  const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
+  if (vp::kick_fused_supported(c->cfg.dtype, nv)) {
+    vp::KickArgs a{};
+    a.f = const_cast<void*>(src);
+    a.out = dst;
+    a.np = c->np;
+    a.reps = 1;
+    for (int l = 0; l < 3; l++) {
+      a.a[l] = c->accel + (long long)l * c->np;
+      a.scale[l] = tau / c->dv[l];
+    }
+    c->f = dst;
+    PhaseScope scope(c, 7);
+    LAUNCH(c, vp::launch_kick(a, c->cfg.dtype, nv, c->stream));
+    return VP_OK;
+  }
+  int r = copy_f(c, dst, src, fbytes);
+  if (r) return r;
+  c->f = dst;
+  return kick(c, tau);
+}
+
 // Reverse mode of nsteps steps of Eq. (17) with checkpoints; see vp.h.
 int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
 {
@@ -871,9 +898,8 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
     const int s0 = seg * k, s1 = (s0 + k < nsteps) ? s0 + k : nsteps;
     st[0] = ck[seg];
     for (int n = s0; n + 1 < s1 && r == VP_OK; n++) {   // recompute the segment's states
-      if ((r = copy_f(c, st[n - s0 + 1], st[n - s0], fb)) || (r = set_accel(n))) break;
-      c->f = st[n - s0 + 1];
-      if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) break;
+      if ((r = set_accel(n))) break;
+      if ((r = kick_to(c, h, st[n - s0], st[n - s0 + 1], fb)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) break;
     }
     c->f = user_f;
     for (int n = s1 - 1; n >= s0 && r == VP_OK; n--) {

@@ -53,6 +53,7 @@ struct KickArgs {
   const double* a[3];
   double scale[3];
   int reps;   // 1: one half kick; 2: two consecutive half kicks with the same acceleration
+  void* out;  // one-pass kick only: write the result here (same layout) instead of over f
 };
 
 // True when a one-pass kernel exists for this velocity grid and element type.

@@ -175,3 +175,24 @@ def test_adjoint_workload_against_finite_differences():
         worst, worst_1e4 = max(worst, err), max(worst_1e4, e4)
     print("worst error on the |g||d| scale: best step", worst, "eps=1e-4", worst_1e4, flush=True)
     assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+def test_grad_same_bits_for_every_checkpoint_interval(bc, dtype):
+    # the states a segment recomputes (first half kick written straight into
+    # the next state's buffer where the velocity block fits on chip, a copy and
+    # an in-place kick otherwise) are those of the forward run, bit for bit
+    w, f0 = _tiny(bc)
+    f0 = f0.astype(NP[dtype]).astype(np.float64)
+    outs = []
+    for ckpt in (1, 2, 3, 8):
+        f = _dev(f0, NP[dtype])
+        sim = Simulator(config_of(w, dtype), f)
+        L, g = sim.grad(w.steps, w.dt, ckpt)
+        outs.append((L, g.cpu().numpy(), f.cpu().numpy()))
+        sim.close()
+    for L, g, fin in outs[1:]:
+        assert L == outs[0][0]
+        assert np.array_equal(g, outs[0][1])
+        assert np.array_equal(fin, outs[0][2])
