@@ -422,27 +422,33 @@ struct PairShape {
 };
 
 template <typename T, int NV, int PASS, int CH_>
-__device__ __forceinline__ void pair_coords(int e, int& gofs, int& lds)
+__device__ __forceinline__ void pair_coords(int e, int& gofs, int& lds, bool fx, bool fy, bool fz)
 {
-  // element e of the slice in HBM order -> offset in the block, LDS index
+  // element e of the slice in HBM order -> offset in the block, LDS index; a
+  // swept axis whose flag is set is held reversed in LDS (the chunk axis never)
   using S = PairShape<T, NV, PASS, CH_>;
+  auto fl = [](bool f, int i) { return f ? NV - 1 - i : i; };
   if constexpr (PASS == 0) {          // runs of CH along vz
     const int run = e / S::CH, c = e - run * S::CH;
     gofs = run * NV + c;             // + c0 added by the caller
-    lds = (run / NV) * S::SA + (run % NV) * S::CH + c;
+    lds = fl(fx, run / NV) * S::SA + fl(fy, run % NV) * S::CH + c;
   } else if constexpr (PASS == 1) {   // per vx, CH whole vz rows
     const int vx = e / (S::CH * NV), rem = e - vx * (S::CH * NV);
     const int c = rem / NV, vz = rem - c * NV;
     gofs = vx * NV * NV + rem;       // + c0 * NV
-    lds = (vx * S::CH + c) * S::SR + vz;
+    lds = (fl(fx, vx) * S::CH + c) * S::SR + fl(fz, vz);
   } else {                            // CH whole vx planes
     const int c = e / (NV * NV), rem = e - c * (NV * NV);
     const int vy = rem / NV, vz = rem - vy * NV;
     gofs = e;                         // + c0 * NV * NV
-    lds = (c * NV + vy) * S::SR + vz;
+    lds = (c * NV + fl(fy, vy)) * S::SR + fl(fz, vz);
   }
 }
 
+// The two swept axes of a slice are held in LDS in the orientation of their
+// sweeps (reversed where the acceleration along them is negative), so both
+// line updates take the forward form with |nu|; the orientation enters only
+// through the LDS places of the loaded and stored pieces.
 template <typename T, int NV, int PASS, int CH_>
 __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_pair_block(KickArgs a)
 {
@@ -454,8 +460,17 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
   const int c0 = (int)(blockIdx.x - s * S::NCH) * CH;
   const long long cofs = PASS == 0 ? c0 : (PASS == 1 ? c0 * NV : c0 * NV * NV);
   T* g = static_cast<T*>(a.f) + s * (long long)(NV * NV * NV) + cofs;
-  // 16-byte pieces: V consecutive values along vz, adjacent in HBM and in LDS;
-  // every load of the lane is issued before the first LDS write
+  // the two sweeps: axis A then axis B (0 = vx, 1 = vy, 2 = vz)
+  constexpr int AX0 = PASS == 0 ? 0 : (PASS == 1 ? 2 : 1);
+  constexpr int AX1 = PASS == 0 ? 1 : (PASS == 1 ? 0 : 2);
+  const double nu0 = a.a[AX0][s] * a.scale[AX0], nu1 = a.a[AX1][s] * a.scale[AX1];
+  const bool f0 = nu0 < 0.0, f1 = nu1 < 0.0;
+  const bool fx = (AX0 == 0 && f0) || (AX1 == 0 && f1);
+  const bool fy = (AX0 == 1 && f0) || (AX1 == 1 && f1);
+  const bool fz = (AX0 == 2 && f0) || (AX1 == 2 && f1);
+  // 16-byte pieces: V consecutive values along vz, adjacent in HBM and in LDS
+  // (descending in LDS where vz is held reversed); every load of the lane is
+  // issued before the first LDS write
   using VT = typename Vec16<T>::type;
   constexpr int V = Vec16<T>::n;
   constexpr int PER = S::HALF / V / S::THREADS;
@@ -465,25 +480,32 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       int go, li;
-      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li);
+      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li, fx, fy, fz);
       x[k] = *reinterpret_cast<const VT*>(g + go);
     }
+    if (fz) {
 #pragma unroll
-    for (int k = 0; k < PER; k++) {
-      int go, li;
-      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li);
+      for (int k = 0; k < PER; k++) {
+        int go, li;
+        pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li, fx, fy, fz);
 #pragma unroll
-      for (int q = 0; q < V; q++) L[li + q] = lane_of<VT, T>(x[k], q);
+        for (int q = 0; q < V; q++) L[li - q] = lane_of<VT, T>(x[k], q);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        int go, li;
+        pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li, fx, fy, fz);
+#pragma unroll
+        for (int q = 0; q < V; q++) L[li + q] = lane_of<VT, T>(x[k], q);
+      }
     }
   }
   __syncthreads();
-  // the two sweeps: axis A then axis B (0 = vx, 1 = vy, 2 = vz)
-  constexpr int AX0 = PASS == 0 ? 0 : (PASS == 1 ? 2 : 1);
-  constexpr int AX1 = PASS == 0 ? 1 : (PASS == 1 ? 0 : 2);
 #pragma unroll
   for (int q = 0; q < 2; q++) {
     const int ax = q == 0 ? AX0 : AX1;
-    const double nu = a.a[ax][s] * a.scale[ax];
+    const double nu = q == 0 ? nu0 : nu1;
     int base, st;
     if constexpr (PASS == 0) {
       // lanes (other in-plane axis, c); vx stride SA, vy stride CH
@@ -510,31 +532,33 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
     T v[NV];
 #pragma unroll
     for (int r = 0; r < NV; r++) v[r] = L[base + r * st];
-    // one code path for both directions (nu is uniform over the block): the
-    // line is mirrored where nu < 0, takes the forward update with |nu|, and
-    // is written back through the mirrored index
-    const bool rev = nu < 0.0;
-#pragma unroll
-    for (int i = 0; i < NV / 2; i++) {
-      const T x0 = v[i], x1 = v[NV - 1 - i];
-      v[i] = rev ? x1 : x0;
-      v[NV - 1 - i] = rev ? x0 : x1;
-    }
     const LineCoef<T> k = line_coef<T, NV>(fabs(nu), false);
     pfc_core<T, NV>(v, k.alpha, k.c1, k.c2, false);
-    const int bw = rev ? base + (NV - 1) * st : base, sw = rev ? -st : st;
-    store_shifted<T, NV>(v, k.shift, false, [&](int r, T x) { L[bw + r * sw] = x; });
+    store_shifted<T, NV>(v, k.shift, false, [&](int r, T x) { L[base + r * st] = x; });
     __syncthreads();
   }
+  if (fz) {
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    int go, li;
-    pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li);
-    VT x;
-    T* xs = reinterpret_cast<T*>(&x);
+    for (int k = 0; k < PER; k++) {
+      int go, li;
+      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li, fx, fy, fz);
+      VT x;
+      T* xs = reinterpret_cast<T*>(&x);
 #pragma unroll
-    for (int q = 0; q < V; q++) xs[q] = L[li + q];
-    *reinterpret_cast<VT*>(g + go) = x;
+      for (int q = 0; q < V; q++) xs[q] = L[li - q];
+      *reinterpret_cast<VT*>(g + go) = x;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      int go, li;
+      pair_coords<T, NV, PASS, CH_>((tid + k * S::THREADS) * V, go, li, fx, fy, fz);
+      VT x;
+      T* xs = reinterpret_cast<T*>(&x);
+#pragma unroll
+      for (int q = 0; q < V; q++) xs[q] = L[li + q];
+      *reinterpret_cast<VT*>(g + go) = x;
+    }
   }
 }
 
