@@ -79,16 +79,20 @@ def build_f(w, torch_dtype, device):
 
 
 def copy_bandwidth(f):
-    """GB/s of a plain device copy of a tensor of f's size (read + write)."""
+    """GB/s (read + write) of the library's plain 16-byte-per-lane copy of a
+    buffer of f's size: the practical HBM ceiling the passes are compared with."""
     import torch
+    from paper_1206_6152_amd._lib import vp_stream_copy
     g = torch.empty_like(f)
-    g.copy_(f)
+    stream = torch.cuda.current_stream().cuda_stream
+    nb = f.numel() * f.element_size()
+    vp_stream_copy(f.data_ptr(), g.data_ptr(), nb, stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 5
     e0.record()
     for _ in range(reps):
-        g.copy_(f)
+        vp_stream_copy(f.data_ptr(), g.data_ptr(), nb, stream)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps

@@ -183,6 +183,14 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 
+/* Measurement aid, no context: dst_dev = src_dev for nbytes bytes on the HIP
+ * stream hip_stream (NULL = default stream), one 16-byte vector per lane. Its
+ * read-and-write rate is the practical HBM ceiling that the sweep passes are
+ * compared with. Both pointers are device memory, 16-byte aligned, and the
+ * ranges must not overlap; nbytes >= 0 is a multiple of 16. Invalid arguments
+ * return VP_EINVAL before any device work. Asynchronous. */
+int vp_stream_copy(const void* src_dev, void* dst_dev, int64_t nbytes, void* hip_stream);
+
 /* ---- reverse mode (gradients; an extension beyond the paper) -------------
  *
  * The loss is the field energy of the final state, L = -U (U of Eq. (41)),

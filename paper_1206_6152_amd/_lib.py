@@ -33,7 +33,7 @@ EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run
            "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_moment", "vp_potential", "vp_energy",
            "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_accel_adjoint",
-           "vp_grad", "vp_free", "vp_last_error"]
+           "vp_grad", "vp_stream_copy", "vp_free", "vp_last_error"]
 VP_NPHASE = 13
 PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity", "kick", "kick2", "drift_yz", "adjoint_sweep",
           "adjoint_gravity", "kick_pair"]
@@ -100,6 +100,7 @@ def lib():
             "vp_sweep_adjoint": [P, i32, f64, P, P, P],
             "vp_accel_adjoint": [P, P, P],
             "vp_grad": [P, i32, f64, i32, P, D],
+            "vp_stream_copy": [P, P, ctypes.c_int64, P],
             "vp_free": [P],
             "vp_last_error": [],
         }
@@ -186,6 +187,11 @@ def vp_density(ctx: int, rho_ptr: int) -> None:
 def vp_moment(ctx: int, a_ptr: int, w_ptr: int, scale: float, out_ptr: int) -> None:
     check(lib().vp_moment(ctx, ctypes.c_void_p(a_ptr), ctypes.c_void_p(w_ptr), float(scale),
                           ctypes.c_void_p(out_ptr)))
+
+
+def vp_stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream_ptr: int) -> None:
+    check(lib().vp_stream_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), ctypes.c_int64(nbytes),
+                               ctypes.c_void_p(stream_ptr)))
 
 
 def vp_potential(ctx: int, phi_ptr: int) -> None:

@@ -554,6 +554,23 @@ hipError_t launch_density(const void* f, int dtype, double* rho, long long np, l
   return hipGetLastError();
 }
 
+// dst = src, one 16-byte vector per lane: the plain read-and-write stream
+// that the sweep passes are measured against
+__global__ __launch_bounds__(256) void copy16_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     long long n)
+{
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t s)
+{
+  if (n16 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const float4*>(src), static_cast<float4*>(dst), n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_weighted_moment(const void* a, int dtype, const double* w, double* out, long long np,
                                   long long nv3, double scale, hipStream_t s)
 {

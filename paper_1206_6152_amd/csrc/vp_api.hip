@@ -979,6 +979,20 @@ int vp_profile_read(vp_ctx* c, double ms_out[VP_NPHASE], int64_t count_out[VP_NP
   return VP_OK;
 }
 
+int vp_stream_copy(const void* src, void* dst, int64_t nbytes, void* hip_stream)
+{
+  g_err.clear();
+  if (!src || !dst) return fail(VP_EINVAL, "null pointer");
+  if (nbytes < 0 || nbytes % 16 != 0) return fail(VP_EINVAL, "nbytes must be a non-negative multiple of 16");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+  if (a % 16 != 0 || b % 16 != 0) return fail(VP_EINVAL, "pointers must be 16-byte aligned");
+  if (nbytes > 0 && a < b + (uintptr_t)nbytes && b < a + (uintptr_t)nbytes)
+    return fail(VP_EINVAL, "source and destination overlap");
+  const hipError_t e = vp::launch_copy16(src, dst, nbytes / 16, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(VP_EHIP, "copy: %s", hipGetErrorString(e));
+  return VP_OK;
+}
+
 int vp_free(vp_ctx* c)
 {
   g_err.clear();

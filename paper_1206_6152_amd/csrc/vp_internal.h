@@ -93,6 +93,9 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s);
 hipError_t launch_density(const void* f, int dtype, double* rho, long long np, long long nv3,
                           double dv3, hipStream_t s);
 
+// dst = src for n16 16-byte vectors (16-byte aligned, not overlapping)
+hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t s);
+
 // out[s] = scale * sum_j a[s*nv3 + j] w[j]
 hipError_t launch_weighted_moment(const void* a, int dtype, const double* w, double* out, long long np,
                                   long long nv3, double scale, hipStream_t s);

@@ -104,3 +104,16 @@ def test_calls_reject_null_context():
     assert L.vp_free(None) == _lib.VP_OK
     with pytest.raises(_lib.VPError):
         _lib.vp_step(None, 0.1)
+
+
+@pytest.mark.parametrize("src,dst,nbytes,why", [
+    (0, 4096, 64, "null"), (4096, 0, 64, "null"),
+    (4096, 8192, 24, "multiple of 16"), (4096, 8192, -16, "multiple of 16"),
+    (4104, 8192, 64, "aligned"), (4096, 8200, 64, "aligned"),
+    (4096, 4112, 64, "overlap"), (4112, 4096, 64, "overlap"), (4096, 4096, 16, "overlap")])
+def test_stream_copy_rejects_bad_arguments_before_device_work(src, dst, nbytes, why):
+    # the addresses are never dereferenced: every case fails host validation
+    _built()
+    with pytest.raises(_lib.VPError) as e:
+        _lib.vp_stream_copy(src, dst, nbytes, 0)
+    assert e.value.code == _lib.VP_EINVAL and why in str(e.value)
