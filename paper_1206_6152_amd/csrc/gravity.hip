@@ -554,20 +554,23 @@ hipError_t launch_density(const void* f, int dtype, double* rho, long long np, l
   return hipGetLastError();
 }
 
-// dst = src, one 16-byte vector per lane: the plain read-and-write stream
-// that the sweep passes are measured against
+// dst = src, one 16-byte vector per lane per round: the plain read-and-write
+// stream that the sweep passes are measured against. A dispatch holds under
+// 2^32 work-items, so the grid is capped and larger copies loop.
 __global__ __launch_bounds__(256) void copy16_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                      long long n)
 {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) dst[i] = src[i];
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 hipError_t launch_copy16(const void* src, void* dst, long long n16, hipStream_t s)
 {
   if (n16 <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s,
-                     static_cast<const float4*>(src), static_cast<float4*>(dst), n16);
+  const long long blocks = (n16 + 255) / 256;
+  const unsigned grid = (unsigned)(blocks < (1LL << 20) ? blocks : (1LL << 20));
+  hipLaunchKernelGGL(copy16_kernel, dim3(grid), dim3(256), 0, s, static_cast<const float4*>(src),
+                     static_cast<float4*>(dst), n16);
   return hipGetLastError();
 }
 
