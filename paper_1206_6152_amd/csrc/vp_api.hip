@@ -879,11 +879,20 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   // forward pass from f0, keeping checkpoints and every step's acceleration
   if ((r = copy_f(c, A(0), c->accel, ab))) return r;
   const double h = 0.5 * dt;
+  // between checkpoints the closing half kick of step n-1 and the opening one
+  // of step n (same acceleration) run as one pass, as in vp_run
+  bool closing = false;   // the closing half kick of the previous step is still due
   for (int n = 0; n < nsteps; n++) {
-    if (n % k == 0 && (r = copy_f(c, ck[n / k], user_f, fb))) return r;
-    if ((r = kick(c, h)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) return r;
+    if (n % k == 0) {
+      if (closing && (r = kick(c, h))) return r;
+      closing = false;
+      if ((r = copy_f(c, ck[n / k], user_f, fb))) return r;
+    }
+    if ((r = kick_n(c, h, closing ? 2 : 1)) || (r = drift_accel(c, dt))) return r;
     if ((r = copy_f(c, A(n + 1), c->accel, ab))) return r;
+    closing = true;
   }
+  if (closing && (r = kick(c, h))) return r;
   if ((r = copy_f(c, fin, user_f, fb))) return r;
   // loss = -U of the final state, seed lam = dL/df = -dx^3 dv^3 phi(x)
   if ((r = potential_into(c, c->phi))) return r;
