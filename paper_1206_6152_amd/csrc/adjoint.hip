@@ -37,8 +37,9 @@ namespace {
 // order then writes out_{i-1} once cell i is known: cell i sends its own terms
 // to out_i, its Lp interior-branch term to out_{i+1} and its Lm interior-branch
 // term to out_{i-1}.
-template <typename T, int N, typename AT>
-__device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at)
+// la(r, x) gives the lam value of cell r from its stored value x
+template <typename T, int N, typename AT, typename LA>
+__device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at, LA la)
 {
 #pragma clang fp contract(off)
   const LineCoef<T> k = line_coef<T, N>(nu, periodic);
@@ -47,7 +48,7 @@ __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool
 #pragma unroll
   for (int r = 0; r < N; r++) {
     w[r] = fin[at(r)];
-    l[r] = lam[at(r)];
+    l[r] = la(r, lam[at(r)]);
   }
   // f_inf and the first storage cell that holds it
   T finf = T(0);
@@ -164,6 +165,12 @@ __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool
   return neg ? -(double)lalpha : (double)lalpha;
 }
 
+template <typename T, int N, typename AT>
+__device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at)
+{
+  return adj_line<T, N>(fin, lam, nu, periodic, at, [](int, T x) { return x; });
+}
+
 __device__ __forceinline__ double adj_line_nu(const SweepArgs& a, long long o, long long c)
 {
   if (a.velocity) return a.accel[o / a.sp_div] * a.scale;
@@ -174,7 +181,7 @@ __device__ __forceinline__ double adj_line_nu(const SweepArgs& a, long long o, l
 // NARROW: the workgroup's first line is the uniform base and a lane's cells sit
 // at base + r*inner + off with a 32-bit offset (the host checks that they fit),
 // as in the forward strided sweep; otherwise 64-bit addressing per lane.
-template <typename T, int N, bool NARROW>
+template <typename T, int N, bool NARROW, bool ADD = false>
 __global__ __launch_bounds__(256) void sweep_adj_kernel(SweepArgs a, const T* fin, T* lam, double* dnu)
 {
   const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -201,8 +208,16 @@ __global__ __launch_bounds__(256) void sweep_adj_kernel(SweepArgs a, const T* fi
       nu = (a.vmin + ((double)j + 0.5) * a.dv) * a.scale;
     }
     // uniform row base (r * inner) plus the lane's 32-bit offset
-    d = adj_line<T, N>(fin + b0, lam + b0, nu, a.periodic != 0,
-                       [&](int r) { return (long long)r * inner + off; });
+    if constexpr (ADD) {
+      const long long o = o0 + dov;
+      const double* add = a.addend + c / (unsigned)a.add_div;
+      d = adj_line<T, N>(fin + b0, lam + b0, nu, a.periodic != 0,
+                         [&](int r) { return (long long)r * inner + off; },
+                         [&](int r, T x) { return (T)((double)x + a.add_coef * add[(o * N + r) * a.add_stride]); });
+    } else {
+      d = adj_line<T, N>(fin + b0, lam + b0, nu, a.periodic != 0,
+                         [&](int r) { return (long long)r * inner + off; });
+    }
   } else {
     const long long o = gid / a.inner;
     const long long c = gid - o * a.inner;
@@ -301,13 +316,18 @@ hipError_t launch_adj_n(const SweepArgs& a, const void* fin, void* lam, double* 
 {
   if (a.nlines <= 0) return hipSuccess;
   if (a.inner == 1) {
+    if (a.addend) return hipErrorInvalidValue;
     constexpr int LINES = AdjContig<T, N>::LINES;
     hipLaunchKernelGGL((sweep_adj_contig<T, N>), dim3((unsigned)((a.nlines + LINES - 1) / LINES)), dim3(LINES), 0, s,
                        a, static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
     return hipGetLastError();
   }
   const long long blocks = (a.nlines + 255) / 256;
-  if (narrow_ok(a, N))
+  if (a.addend) {
+    if (!narrow_ok(a, N)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_adj_kernel<T, N, true, true>), dim3((unsigned)blocks), dim3(256), 0, s, a,
+                       static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
+  } else if (narrow_ok(a, N))
     hipLaunchKernelGGL((sweep_adj_kernel<T, N, true>), dim3((unsigned)blocks), dim3(256), 0, s, a,
                        static_cast<const T*>(fin), static_cast<T*>(lam), dnu);
   else
@@ -339,6 +359,11 @@ hipError_t launch_adj_t(const SweepArgs& a, const void* fin, void* lam, double* 
 }
 
 }  // namespace
+
+bool adjoint_addend_supported(const SweepArgs& a)
+{
+  return a.inner > 1 && a.add_div > 0 && narrow_ok(a, a.n);
+}
 
 hipError_t launch_sweep_adjoint(const SweepArgs& a, int dtype, const void* fin, void* lam, double* dnu,
                                 hipStream_t s)

@@ -307,9 +307,22 @@ bool x_sweep_sums(vp_ctx* c)
 
 // lam <- J^T lam of T_axis(tau) at forward input fin; velocity axes add the
 // acceleration adjoint to lam_a (if not null).
-int sweep_adjoint(vp_ctx* c, int axis, double tau, const void* fin, void* lam, double* lam_a)
+int sweep_adjoint(vp_ctx* c, int axis, double tau, const void* fin, void* lam, double* lam_a,
+                  const double* rho_adj = nullptr)
 {
-  const vp::SweepArgs a = sweep_args(c, axis, tau);
+  vp::SweepArgs a = sweep_args(c, axis, tau);
+  if (rho_adj) {   // lam += dv^3 rho_adj(spatial cell) first: fused into the loads where supported
+    const double dv3 = c->dv[0] * c->dv[1] * c->dv[2];
+    a.addend = rho_adj;
+    a.add_coef = dv3;
+    a.add_stride = a.inner / c->nv3;
+    a.add_div = c->nv3;
+    if (axis >= 3 || a.inner % c->nv3 != 0 || !vp::adjoint_addend_supported(a)) {
+      a.addend = nullptr;
+      PhaseScope scope(c, 11);
+      LAUNCH(c, vp::launch_broadcast_add(lam, c->cfg.dtype, rho_adj, c->np, c->nv3, dv3, c->stream));
+    }
+  }
   const bool want = axis >= 3 && lam_a;
   if (want && a.nlines > c->dnu_len) {
     hipFree(c->dnu);
@@ -329,8 +342,9 @@ int sweep_adjoint(vp_ctx* c, int axis, double tau, const void* fin, void* lam, d
   return VP_OK;
 }
 
-// lam += dv^3 G^T D^T lam_a: transpose of density -> potential -> acceleration
-int accel_adjoint(vp_ctx* c, const double* lam_a, void* lam)
+// c->radj = G^T D^T lam_a: transpose of potential -> acceleration, per spatial
+// cell (the density adjoint; lam then gains dv^3 times it)
+int density_adjoint(vp_ctx* c, const double* lam_a)
 {
   const long long ext = (long long)(c->cfg.n[0] + 2) * (c->cfg.n[1] + 2) * (c->cfg.n[2] + 2);
   int r;
@@ -352,6 +366,15 @@ int accel_adjoint(vp_ctx* c, const double* lam_a, void* lam)
     for (int ax = 0; ax < 3; ax++) LAUNCH(c, vp::launch_dft_axis(c->work, c->wg, ax, +1, c->tw[ax], c->stream));
     LAUNCH(c, vp::launch_extract_interior(c->radj, c->work, c->wg, c->ng, 1.0 / (double)prod3(c->wg.m), c->stream));
   }
+  return VP_OK;
+}
+
+// lam += dv^3 G^T D^T lam_a: transpose of density -> potential -> acceleration
+int accel_adjoint(vp_ctx* c, const double* lam_a, void* lam)
+{
+  int r = density_adjoint(c, lam_a);
+  if (r) return r;
+  PhaseScope scope(c, 11);
   LAUNCH(c, vp::launch_broadcast_add(lam, c->cfg.dtype, c->radj, c->np, c->nv3, c->dv[0] * c->dv[1] * c->dv[2],
                                      c->stream));
   return VP_OK;
@@ -923,8 +946,11 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
       // second half kick (acceleration a_{n+1}), then a_{n+1} = A(state after the drift)
       if ((r = copy_f(c, lam_a, lam_p, ab))) break;
       for (int q = 8; q >= 6 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, in[q], lam, lam_a);
-      if (r || (r = accel_adjoint(c, lam_a, lam))) break;
-      for (int q = 5; q >= 3 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], dt, in[q], lam, nullptr);
+      // the density adjoint's contribution to lam rides on the loads of the
+      // reverse x sweep that follows
+      if (r || (r = density_adjoint(c, lam_a))) break;
+      for (int q = 5; q >= 3 && r == VP_OK; q--)
+        r = sweep_adjoint(c, axes[q], dt, in[q], lam, nullptr, q == 5 ? c->radj : nullptr);
       if (r) break;
       if ((r = set_accel(n))) break;
       HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));

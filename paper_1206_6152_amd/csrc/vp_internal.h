@@ -27,6 +27,12 @@ struct SweepArgs {
   double vmin, dv;     // cell-centre velocity v_j = vmin + (j + 1/2) dv
   double* part;        // optional: per-workgroup sums of the new line values (see below)
   void* out;           // optional: write the result here (same layout) instead of over f
+  // reverse sweeps only, optional: each lam value is first raised by
+  // add_coef * addend[spatial cell] (the spatial cell of line (o, c), cell r is
+  // (o*n + r) * add_stride + c / add_div)
+  const double* addend;
+  double add_coef;
+  long long add_stride, add_div;
 };
 
 // Launch one sweep on the stream; dtype 0 = float, 1 = double.
@@ -161,9 +167,12 @@ hipError_t launch_accel_max(double* out, const double* accel, long long np, doub
 // ---- reverse mode -------------------------------------------------------------
 
 // lam <- J^T lam for the sweep described by a at forward input fin; the
-// per-line d<lam, out>/d nu goes to dnu[line] when dnu is not null.
+// per-line d<lam, out>/d nu goes to dnu[line] when dnu is not null. With
+// a.addend set, lam is first raised by the addend (strided lines with compact
+// addressing only: adjoint_addend_supported).
 hipError_t launch_sweep_adjoint(const SweepArgs& a, int dtype, const void* fin, void* lam, double* dnu,
                                 hipStream_t s);
+bool adjoint_addend_supported(const SweepArgs& a);
 // lam_a[s] += scale * sum_{i < per} dnu[s*per + i], s < np
 hipError_t launch_reduce_lines(double* lam_a, const double* dnu, long long np, long long per, double scale,
                                hipStream_t s);
