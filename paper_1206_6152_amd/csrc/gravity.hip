@@ -111,17 +111,30 @@ __global__ __launch_bounds__(RED) void weighted_moment_kernel(const T* a, const 
 
 // One thread per spatial cell (x, yz), x fastest so a wave reads whole rows of
 // the workgroup sums; the velocity chunks are added in their index order.
+// One workgroup per spatial (y, z) column: lane t takes x = t % n and chunk
+// group g = t / n (G = 256 / n groups), adds the chunks k = g, g + G, ... in
+// order, and the G group sums of each x are then added in order of g. The
+// order is fixed, so the result is deterministic.
 __global__ __launch_bounds__(256) void density_from_parts_kernel(double* rho, const double* part, long long nyz,
                                                                  long long nchunk, int n, double dv3)
 {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= nyz * n) return;
-  const long long yz = i / n;
-  const int x = (int)(i - yz * n);
-  const double* p = part + yz * nchunk * n + x;
+  __shared__ double sums[256];
+  const long long yz = blockIdx.x;
+  const int t = threadIdx.x;
+  const int G = 256 / n;
+  const int x = t % n, g = t / n;
   double acc = 0.0;
-  for (long long k = 0; k < nchunk; k++) acc += p[k * n];
-  rho[(long long)x * nyz + yz] = acc * dv3;
+  if (g < G) {
+    const double* p = part + yz * nchunk * n + x;
+    for (long long k = g; k < nchunk; k += G) acc += p[k * n];
+  }
+  sums[t] = acc;
+  __syncthreads();
+  if (t < n) {
+    double tot = 0.0;
+    for (int q = 0; q < G; q++) tot += sums[q * n + t];
+    rho[(long long)t * nyz + yz] = tot * dv3;
+  }
 }
 
 __global__ void twiddle_kernel(double2* w, int M)
@@ -592,8 +605,8 @@ hipError_t launch_density_from_parts(double* rho, const double* part, long long 
 {
   const long long cells = nyz * n;
   if (cells <= 0) return hipSuccess;
-  hipLaunchKernelGGL(density_from_parts_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, rho, part,
-                     nyz, nchunk, n, dv3);
+  hipLaunchKernelGGL(density_from_parts_kernel, dim3((unsigned)nyz), dim3(256), 0, s, rho, part, nyz, nchunk, n,
+                     dv3);
   return hipGetLastError();
 }
 
