@@ -191,6 +191,14 @@ int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_
  * return VP_EINVAL before any device work. Asynchronous. */
 int vp_stream_copy(const void* src_dev, void* dst_dev, int64_t nbytes, void* hip_stream);
 
+/* Integral of 1/|r| over one cell of widths dx, dy, dz centred on the origin.
+ * The paper's isolated Green's function (Sec. 2.2, Eq. (21)) is G/r and says
+ * nothing of the cell's own offset; this library reads the kernel as
+ * -G dx dy dz / |r| away from zero and -G times this integral at zero (the
+ * potential of a uniform cell at its centre). Pure host arithmetic, no device
+ * and no context; returns NaN unless all three widths are finite and > 0. */
+double vp_cell_self_integral(double dx, double dy, double dz);
+
 /* ---- reverse mode (gradients; an extension beyond the paper) -------------
  *
  * The loss is the field energy of the final state, L = -U (U of Eq. (41)),

@@ -33,7 +33,8 @@ EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run
            "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_moment", "vp_potential", "vp_energy",
            "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_accel_adjoint",
-           "vp_grad", "vp_stream_copy", "vp_free", "vp_last_error"]
+           "vp_grad", "vp_stream_copy", "vp_cell_self_integral", "vp_free",
+           "vp_last_error"]
 VP_NPHASE = 13
 PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity", "kick", "kick2", "drift_yz", "adjoint_sweep",
           "adjoint_gravity", "kick_pair"]
@@ -109,6 +110,8 @@ def lib():
             fn.argtypes = args
             fn.restype = ctypes.c_int
         L.vp_last_error.restype = ctypes.c_char_p
+        L.vp_cell_self_integral.argtypes = [f64, f64, f64]
+        L.vp_cell_self_integral.restype = f64
         if L.vp_config_size() != ctypes.sizeof(vp_config):
             raise RuntimeError("vp_config layout mismatch between libvp.so and the binding")
         _lib = L
@@ -192,6 +195,10 @@ def vp_moment(ctx: int, a_ptr: int, w_ptr: int, scale: float, out_ptr: int) -> N
 def vp_stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream_ptr: int) -> None:
     check(lib().vp_stream_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), ctypes.c_int64(nbytes),
                                ctypes.c_void_p(stream_ptr)))
+
+
+def vp_cell_self_integral(dx: float, dy: float, dz: float) -> float:
+    return float(lib().vp_cell_self_integral(float(dx), float(dy), float(dz)))
 
 
 def vp_potential(ctx: int, phi_ptr: int) -> None:

@@ -109,8 +109,6 @@ __global__ __launch_bounds__(RED) void weighted_moment_kernel(const T* a, const 
   if (threadIdx.x == 0) out[blockIdx.x] = s * scale;
 }
 
-// One thread per spatial cell (x, yz), x fastest so a wave reads whole rows of
-// the workgroup sums; the velocity chunks are added in their index order.
 // One workgroup per spatial (y, z) column: lane t takes x = t % n and chunk
 // group g = t / n (G = 256 / n groups), adds the chunks k = g, g + G, ... in
 // order, and the G group sums of each x are then added in order of g. The

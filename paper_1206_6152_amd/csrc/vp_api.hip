@@ -3,6 +3,7 @@
 // kernels of one step of Eq. (17) (Yoshikawa, Yoshida & Umemura, Sec. 2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -103,17 +104,76 @@ int check_launch(vp_ctx* c, hipError_t e, const char* what)
     if (r_ != VP_OK) return r_;                         \
   } while (0)
 
-// Integral of 1/|r| over [0,a]x[0,b]x[0,c] (closed form for the potential of a
-// uniform box at a corner); eight of them give the cell self term.
-double corner_integral(double a, double b, double c)
+// Gauss-Legendre rule of order n on [-1, 1]: nodes are the roots of P_n,
+// found by Newton's method from the estimate cos(pi (i + 3/4) / (n + 1/2)),
+// with P_n and P_n' from Bonnet's three-term recurrence; weights
+// 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, double* x, double* w)
 {
-  const double d = std::sqrt(a * a + b * b + c * c);
-  return a * b * std::log((c + d) / std::sqrt(a * a + b * b)) +
-         b * c * std::log((a + d) / std::sqrt(b * b + c * c)) +
-         c * a * std::log((b + d) / std::sqrt(c * c + a * a)) -
-         0.5 * a * a * std::atan(b * c / (a * d)) - 0.5 * b * b * std::atan(c * a / (b * d)) -
-         0.5 * c * c * std::atan(a * b / (c * d));
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (n + 1) / 2; i++) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; it++) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; k++) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
 }
+
+}  // namespace
+
+// Integral of 1/|r| over the cell of widths dx, dy, dz centred on the origin: the
+// potential of a unit-density cell at its own centre, which is the isolated
+// kernel's value at zero offset. Since div(r/|r|) = 2/|r|, the divergence
+// theorem makes the volume integral half the outward flux of r/|r|; on the two
+// faces normal to axis l, r.n = h_l (the half width), so
+//   I = sum_l h_l int_{face l} dA / |r|.
+// Across one face coordinate the integrand has the antiderivative asinh, so
+//   int_face dA/|r| = 4 int_0^{h_b} asinh(h_c / sqrt(h_l^2 + y^2)) dy,
+// a smooth integrand (its nearest complex singularity is at y = i h_l),
+// integrated with 16-point Gauss-Legendre panels no wider than h_l / 2.
+double vp_cell_self_integral(double dx, double dy, double dz)
+{
+  if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx + dy + dz)) return NAN;
+  const int NG = 16;
+  double gx[NG], gw[NG];
+  gauss_legendre(NG, gx, gw);
+  const double h[3] = {0.5 * dx, 0.5 * dy, 0.5 * dz};
+  double total = 0.0;
+  for (int l = 0; l < 3; l++) {
+    const double hl = h[l];
+    for (int t = 0; t < 2; t++) {  // (hb, hc) and (hc, hb): the face integral both ways, averaged
+      const double hb = h[(l + 1 + t) % 3], hc = h[(l + 2 - t) % 3];
+      const long panels = std::max(1L, (long)std::ceil(2.0 * hb / hl));
+      const double width = hb / panels;
+      double face = 0.0;
+      for (long p = 0; p < panels; p++) {
+        const double mid = (p + 0.5) * width;
+        double acc = 0.0;
+        for (int g = 0; g < NG; g++) {
+          const double y = mid + 0.5 * width * gx[g];
+          acc += gw[g] * std::asinh(hc / std::sqrt(hl * hl + y * y));
+        }
+        face += 0.5 * width * acc;
+      }
+      total += 0.5 * hl * 4.0 * face;
+    }
+  }
+  return total;
+}
+
+namespace {
 
 void release(vp_ctx* c)
 {
@@ -612,7 +672,7 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
     }
   }
   if (cfg->bc == VP_BC_ISOLATED) {
-    const double self = -cfg->G * 8.0 * corner_integral(0.5 * c->dx[0], 0.5 * c->dx[1], 0.5 * c->dx[2]);
+    const double self = -cfg->G * vp_cell_self_integral(c->dx[0], c->dx[1], c->dx[2]);
     r = check_launch(c, vp::launch_green_isolated(c->kspec, c->wg, cfg->G, c->dx[0], c->dx[1], c->dx[2], self,
                                                   c->stream), "green");
     for (int ax = 0; ax < 3 && r == VP_OK; ax++)

@@ -108,7 +108,9 @@ hipError_t launch_weighted_moment(const void* a, int dtype, const double* w, dou
 
 // rho from the x sweep's workgroup sums: spatial column yz (of nyz) has
 // nchunk workgroups, each with n sums (one per x);
-// rho[x*nyz + yz] = dv3 * sum_k part[(yz*nchunk + k)*n + x], k in order.
+// rho[x*nyz + yz] = dv3 * sum_k part[(yz*nchunk + k)*n + x]. With G = 256/n
+// chunk groups, group g adds the chunks k = g, g + G, ... in order, and the G
+// group sums are then added in order of g (a fixed order, deterministic).
 hipError_t launch_density_from_parts(double* rho, const double* part, long long nyz, long long nchunk, int n,
                                      double dv3, hipStream_t s);
 

@@ -335,6 +335,20 @@ def king_f(w: Workload, scale: float = 1.0) -> np.ndarray:
     return np.where(E > 0, pref * np.expm1(np.maximum(E, 0.0)), 0.0)
 
 
+def king_spheres_f(w: Workload, scale: float = 1.0) -> np.ndarray:
+    """Sum over the workload's spheres (centre c, bulk velocity u) of the King
+    distribution function with E = Psi(|x - c|) - |v - u|^2 / 2, at cell centres, on
+    the host in FP64 (for grids small enough to hold there), times scale."""
+    pref = king_prefactor(w.params["W0"]) * scale
+    f = np.zeros(w.shape, dtype=np.float64)
+    for psi, vrel in king_sphere_fields(w):
+        V = np.meshgrid(*vrel, indexing="ij")
+        hv2 = 0.5 * (V[0] ** 2 + V[1] ** 2 + V[2] ** 2)
+        E = psi.reshape(psi.shape + (1, 1, 1)) - hv2.reshape((1, 1, 1) + hv2.shape)
+        f += np.where(E > 0, pref * np.expm1(np.maximum(E, 0.0)), 0.0)
+    return f
+
+
 def king_psi(w: Workload) -> np.ndarray:
     """Psi(x)/sigma^2 at spatial cell centres (0 outside the tidal radius)."""
     model = king_model(w.params["W0"])

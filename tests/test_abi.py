@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1206_6152_amd import _lib
@@ -117,3 +118,21 @@ def test_stream_copy_rejects_bad_arguments_before_device_work(src, dst, nbytes, 
     with pytest.raises(_lib.VPError) as e:
         _lib.vp_stream_copy(src, dst, nbytes, 0)
     assert e.value.code == _lib.VP_EINVAL and why in str(e.value)
+
+
+@pytest.mark.parametrize("d", [(1.0, 1.0, 1.0), (0.75, 0.75, 0.75), (1.0, 2.0, 0.5), (0.3, 1.7, 1.1), (1e-3, 1.0, 1.0)])
+def test_cell_self_integral_matches_the_oracles_closed_form(orc, d):
+    # Two independent derivations of the isolated kernel's self term (Sec. 2.2):
+    # the library's divergence-theorem quadrature (host code, no device) and
+    # the oracle's closed form for a box seen from a corner.
+    _built()
+    got = _lib.vp_cell_self_integral(*d)
+    np.testing.assert_allclose(got, orc.cell_self_integral(*d), rtol=1e-13)
+    # scaling: the integral of 1/|r| over a volume scales as length^2
+    np.testing.assert_allclose(_lib.vp_cell_self_integral(*(3 * x for x in d)), 9 * got, rtol=1e-13)
+
+
+def test_cell_self_integral_rejects_bad_widths():
+    _built()
+    for d in [(0.0, 1.0, 1.0), (1.0, -1.0, 1.0), (1.0, 1.0, float("nan")), (float("inf"), 1.0, 1.0)]:
+        assert np.isnan(_lib.vp_cell_self_integral(*d))

@@ -55,6 +55,43 @@ def test_step_density_from_x_sweep_sums(dtype, nx, bc):
     assert rel_l1(fa, run.f) <= (1e-13 if dtype == VP_F64 else 2e-6)
 
 
+@pytest.mark.parametrize("dtype,nx", [(VP_F32, 32), (VP_F64, 32), (VP_F32, 4)])
+def test_step_density_from_strided_chunk_groups(dtype, nx):
+    # 32^3 velocity cells: 128 chunks of 256 per spatial column. With nx = 32
+    # there are 8 chunk groups, each lane adding 16 chunks (the grouping of the
+    # benchmark workloads); nx = 4 gives 64 groups of 2 chunks.
+    import torch
+    print("case", dtype, nx, flush=True)
+    w = inputs.Workload(name="s", n=(nx, 2, 2), nv=(32, 32, 32), L=(0.25 * nx, 0.5, 0.5), vmin=(-1.0, -2.0, -1.5),
+                        vmax=(1.5, 2.0, 1.5), G=2.0, bc=VP_BC_PERIODIC)
+    rng = np.random.default_rng(100 + nx)
+    f0 = (structured_f(w.shape, seed=nx) + 1e-3 * rng.uniform(0, 1, w.shape)).astype(NP[dtype]).astype(np.float64)
+    dt = 0.05
+    outs = []
+    for mode in ("step", "parts"):
+        f = torch.from_numpy(np.ascontiguousarray(f0.astype(NP[dtype]))).to("cuda:0")
+        sim = Simulator(config_of(w, dtype), f)
+        if mode == "step":
+            sim.step(dt)
+        else:
+            sim.kick(0.5 * dt)
+            sim.drift(dt)
+            sim.accel()
+            sim.kick(0.5 * dt)
+        outs.append((f.cpu().numpy().astype(np.float64), sim.get_accel().cpu().numpy()))
+        sim.close()
+    (fa, aa), (fb, ab) = outs
+    assert np.abs(aa - ab).max() <= 1e-12 * np.abs(ab).max()
+    assert rel_l1(fa, fb) <= (1e-14 if dtype == VP_F64 else 1e-6)
+    g = oracle_grid(w)
+    run = oracle.Run(g, f0)
+    run.step(dt)
+    # the acceleration the step left behind comes from the x-sweep sums; the
+    # oracle's comes from its own density of the drifted f
+    np.testing.assert_allclose(aa, run.a, rtol=0, atol=(1e-12 if dtype == VP_F64 else 2e-6) * np.abs(run.a).max())
+    assert rel_l1(fa, run.f) <= (1e-13 if dtype == VP_F64 else 2e-6)
+
+
 @pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
 def test_run_with_x_sweep_sums_matches_oracle(dtype):
     # several steps of the fused path (kick pairs, one-pass drift, x sweep sums)

@@ -16,7 +16,7 @@ import math
 import numpy as np
 import pytest
 
-from paper_1206_6152_amd import VP_F32, Simulator, config_of, inputs
+from paper_1206_6152_amd import VP_F32, VP_F64, Simulator, config_of, inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -161,3 +161,81 @@ def test_6_two_king_spheres_merge():
     assert 3.0 <= t[np.argmax(peak)] <= 4.5
     # ... and they pass through each other
     assert d[-1] > 3 * d[t <= 3.0 + 1e-9].min()
+
+
+def _king_w6_run(w, until_T=None, steps=None, dtype=VP_F32):
+    """Virial-renormalised W0 = 6 sphere on grid w, stepped with the Courant
+    step C = 0.5 of Sec. 2.4 re-evaluated from each state; returns the
+    energies (K, U, M, E) after every step, the times and min f."""
+    import torch
+    spheres = ((inputs.king_psi(w), [w.vc(l) for l in range(3)]),)
+    s = _virial_scale(w, spheres)
+    f = _king_f(w, spheres)
+    f.mul_(s)
+    if dtype == VP_F64:
+        f = f.double()
+    sim = Simulator(config_of(w, dtype), f)
+    T = inputs.king_units(6.0)[2]
+    e, ts, t = [sim.energy()], [0.0], 0.0
+    while (steps is not None and len(ts) <= steps) or (until_T is not None and t < until_T * T):
+        dt = sim.dt(0.5)
+        sim.step(dt)
+        t += dt
+        e.append(sim.energy())
+        ts.append(t)
+    fmin = float(f.min())
+    sim.close()
+    del f
+    torch.cuda.empty_cache()
+    return np.array(e), np.array(ts) / T, fmin, s
+
+
+def test_king_w6_48_cubed_hundred_courant_steps():
+    # The King workload as specified: W0 = 6, 48^3 x 48^3 cells in FP32 (49 GB),
+    # isolated, 100 steps with the Courant step C = 0.5 of Sec. 2.4 re-evaluated
+    # from each state, the distribution function renormalised to 2K/|U| = 1 on
+    # the grid as the paper does for its King spheres (Sec. 3.5). Sec. 3.5
+    # reports M within ~1e-4 and E within ~1 % over one dynamical time T for a
+    # W = 3 sphere resolved by 0.17 r0 cells. Here the box spans the tidal
+    # radius (18 r0) with 48 cells, so a cell is 0.75 r0 and the core is barely
+    # resolved; 100 steps cover about 30 T. Measured: M drifts 8e-6 (mass is
+    # held), E drifts 3 % by 2.3 T and 14 % by 30 T; the spatial resolution
+    # sets it (test_king_w6_energy_drift_falls_with_spatial_resolution).
+    print("king w6 48^3 x 48^3, 100 steps", flush=True)
+    w = inputs.king_48_48()
+    e, tT, fmin, s = _king_w6_run(w, steps=100)
+    K0, U0, M0, E0 = e[0]
+    dM = np.abs(e[:, 2] - M0) / M0
+    dE = np.abs(e[:, 3] - E0) / abs(E0)
+    for i in list(range(0, 11)) + list(range(20, 101, 10)):
+        K, U, M, E = e[i]
+        print("step %3d  t %.3f T  2K/|U| %.4f  dM/M %.2e  dE/|E| %.2e" % (
+            i, tT[i], 2 * K / abs(U), (M - M0) / M0, (E - E0) / abs(E0)), flush=True)
+    i1 = int(np.searchsorted(tT, 1.0))
+    print("virial scale %.5f  100 steps = %.2f T  max |dM/M| %.2e  |dE/E| at %.2f T %.2e, at 100 steps %.2e" % (
+        s, tT[-1], dM.max(), tT[i1], dE[i1], dE[-1]), flush=True)
+    assert fmin >= 0.0
+    assert abs(2 * K0 / abs(U0) - 1) < 1e-5
+    assert dM.max() < 1e-4                        # Sec. 3.5: mass within ~1e-4
+    assert dE[i1] < 0.03 and dE.max() < 0.2      # measured 3 % by 2.3 T, 14 % at 30 T (cause above)
+
+
+def test_king_w6_energy_drift_falls_with_spatial_resolution():
+    # Same sphere and box (+-r_t = +-18 r0) and velocity grid (32^3), spatial
+    # cells 24^3, 32^3, 48^3, 64^3 (0.75 r0 at 48): the energy drift over one
+    # dynamical time falls as the core becomes resolved, so it is the spatial
+    # discretisation, not the integrator or the storage precision, that sets the
+    # King workload's drift.
+    print("king w6 resolution study", flush=True)
+    base = inputs.king_48_48()
+    drift = {}
+    for n in (24, 32, 48, 64):
+        w = base.with_grid(n=(n,) * 3, nv=(32,) * 3)
+        e, tT, fmin, s = _king_w6_run(w, until_T=1.0)
+        dE = abs(e[-1, 3] - e[0, 3]) / abs(e[0, 3])
+        dM = abs(e[-1, 2] - e[0, 2]) / e[0, 2]
+        drift[n] = dE
+        print("n %2d (dx %.3f r0): %d steps to %.2f T, |dE/E| %.2e, |dM/M| %.2e" % (
+            n, w.dx(0), len(tT) - 1, tT[-1], dE, dM), flush=True)
+        assert fmin >= 0.0 and dM < 1e-4
+    assert drift[64] < drift[48] < drift[32] < drift[24]

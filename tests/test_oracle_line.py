@@ -175,3 +175,74 @@ def test_single_cell_lines(orc):
     np.testing.assert_allclose(orc.line(f, 0.0, False), f, rtol=0)
     # outflow: a single cell loses the fraction nu of a flat profile
     np.testing.assert_allclose(orc.line(f, 0.3, False), [0.4 * 0.7], rtol=1e-15)
+
+
+def _steep_cases():
+    # Cell averages of a parabola whose one-sided differences sit between one
+    # and two times the distance to the bound the corrector guards (Sec. 2.1,
+    # slope corrector of the PFC scheme). With the corrector's factor 2 the
+    # parabola is left exact on those cells; a factor 1 would cut the slope.
+    #   rise:  q(x) = (x - s)^2 on cells centred at integers right of the
+    #          minimum (eps+ against 2 f): for s = 0 the cell at 2 has
+    #          D+/f = 5/(4 + 1/12) = 1.22; for s = -1/2 the cell centred at
+    #          1.5 has D+/f = 4/(2.25 + 1/12) = 1.71.
+    #   fall:  the mirror image, left of the minimum (eps- against 2 f).
+    #   cap:   q(x) = A - x^2, line maximum f_inf = A - 1/12 at cell 0. The
+    #          cell at -2 has D-/(f_inf - f) = 5/4 (eps- against f_inf) and the
+    #          cell at +2 has |D+|/(f_inf - f) = 5/4 (eps+ against f_inf).
+    cases = []
+    for s in (0.0, -0.5):
+        P = lambda x, s=s: (x - s) ** 3 / 3.0
+        cases.append(("rise", P, np.arange(0, 24) + 0.0))
+        P = lambda x, s=s: (x + s) ** 3 / 3.0
+        cases.append(("fall", P, np.arange(-23, 1) + 0.0))
+    A = 50.0
+    P = lambda x: A * x - x ** 3 / 3.0
+    cases.append(("cap", P, np.arange(-6, 7) + 0.0))
+    return cases
+
+
+def _used_cells(i, nu):
+    # cells whose profile the update of cell i integrates over
+    a, b = i - 0.5 - nu, i + 0.5 - nu
+    return set(range(int(np.floor(a + 0.5)), int(np.floor(b + 0.5)) + 1))
+
+
+@pytest.mark.parametrize("nu", [-1.6, -0.7, -0.3, 0.2, 0.55, 0.85, 1.4])
+def test_steep_quadratic_cell_averages_advect_exactly_under_the_correctors(orc, nu):
+    hit = 0
+    branches = set()
+    for kind, P, centres in _steep_cases():
+        f = P(centres + 0.5) - P(centres - 0.5)
+        assert f.min() > 0.0
+        finf = f.max()
+        # the corrector each difference meets and the bound it is held to
+        bounds = []
+        for k in range(len(f)):
+            row = {}
+            if k + 1 < len(f):
+                d = f[k + 1] - f[k]
+                row["+"] = (abs(d), 2 * f[k] if d > 0 else 2 * (finf - f[k]), "eps+ f" if d > 0 else "eps+ finf")
+            if k > 0:
+                d = f[k] - f[k - 1]
+                row["-"] = (abs(d), 2 * (finf - f[k]) if d > 0 else 2 * f[k], "eps- finf" if d > 0 else "eps- f")
+            bounds.append(row)
+        # unlimited with the factor 2: every difference within its bound
+        exact_ok = np.array([len(b) == 2 and all(d <= bd for d, bd, _ in b.values()) for b in bounds])
+        # steep: unlimited with the factor 2, limited with a factor 1
+        steep_j = [k for k, b in enumerate(bounds)
+                   if exact_ok[k] and any(d > 0.5 * bd for d, bd, _ in b.values())]
+        assert steep_j, kind
+        out = orc.line(f, nu, periodic=False, limited=True)
+        exact = (P(centres + 0.5 - nu) - P(centres - 0.5 - nu))
+        for i in range(len(f)):
+            used = _used_cells(i, nu)
+            if not all(0 <= k < len(f) and exact_ok[k] for k in used):
+                continue
+            np.testing.assert_allclose(out[i], exact[i], rtol=1e-13, err_msg="%s cell %d" % (kind, i))
+            for k in used & set(steep_j):
+                hit += 1
+                branches.update(name for d, bd, name in bounds[k].values() if d > 0.5 * bd)
+    # updates that read a steep cell were checked, for each of the four bounds
+    assert hit >= 5
+    assert branches == {"eps+ f", "eps+ finf", "eps- f", "eps- finf"}
