@@ -231,6 +231,24 @@ int vp_sweep_adjoint(vp_ctx* ctx, int32_t axis, double tau, const void* f_in_dev
 int vp_accel_adjoint(vp_ctx* ctx, const double* lam_accel_dev, void* lam_dev);
 int vp_grad(vp_ctx* ctx, int32_t nsteps, double dt, int32_t ckpt_every, void* grad_f0_dev, double* loss_host);
 
+/* vp_sweep_adjoint_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, same kernels and the same result bit for bit as
+ * vp_sweep_adjoint, but it calls no hipMalloc, hipFree or other allocating
+ * routine: the per-line adjoints of a velocity sweep's Courant numbers live
+ * in a static device array of VP_NOALLOC_MAX_LINES doubles (32 MiB), which
+ * each device the library runs on holds until the process ends (its address
+ * is resolved per device by vp_init). A velocity sweep with lam_accel_dev set
+ * and more lines than that (N_cells / Nv_axis > VP_NOALLOC_MAX_LINES) returns
+ * VP_EINVAL before any device work. The array is shared by every call on a
+ * device and keeps the last call's contents (each call overwrites every entry
+ * it reads, so nothing has to start at zero); calls that overlap in time on
+ * one device, from any contexts or streams, race on it. No phase timing is
+ * recorded for this call. */
+#define VP_NOALLOC_MAX_LINES 4194304
+int vp_sweep_adjoint_noalloc(vp_ctx* ctx, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,
+                             double* lam_accel_dev);
+
 /* Release everything the context owns (never f). NULL is accepted. */
 int vp_free(vp_ctx* ctx);
 

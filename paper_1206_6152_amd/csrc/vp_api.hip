@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -78,7 +79,41 @@ struct vp_ctx {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double phase_ms[VP_NPHASE] = {};
   long long phase_n[VP_NPHASE] = {};
+  // this device's address of the static scratch array (vp_sweep_adjoint_noalloc)
+  double* scratch = nullptr;
 };
+
+// Scratch of vp_sweep_adjoint_noalloc: the per-line adjoint of the Courant
+// number of one velocity sweep, one double per line, VP_NOALLOC_MAX_LINES lines
+// (32 MiB). It is a static device array, so every device the library runs on
+// holds its own copy from code-object load until the process ends. In host
+// code the name is a host-side stand-in, never a device address: host code
+// uses only the per-device address from hipGetSymbolAddress (scratch_address).
+__device__ __align__(256) double scratch[VP_NOALLOC_MAX_LINES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, resolved once per device (the
+// caller has made `device` current). Called from vp_init.
+int scratch_address(int device, double** out)
+{
+  if (device < 0 || device >= kMaxDevices) return fail(VP_EUNSUPPORTED, "device index %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(VP_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_addr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[device];
+  return VP_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -623,6 +658,10 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
     delete c;
     return fail(VP_EHIP, "device query: %s", hipGetErrorString(de));
   }
+  if ((r = scratch_address(c->device, &c->scratch))) {
+    delete c;
+    return r;
+  }
   for (int l = 0; l < 3; l++) {
     c->dx[l] = cfg->L[l] / cfg->n[l];
     c->dv[l] = (cfg->vmax[l] - cfg->vmin[l]) / cfg->nv[l];
@@ -865,6 +904,32 @@ int vp_sweep_adjoint(vp_ctx* c, int32_t axis, double tau, const void* f_in_dev, 
   if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
   if (!f_in_dev || !lam_dev) return fail(VP_EINVAL, "null pointer");
   return sweep_adjoint(c, axis, tau, f_in_dev, lam_dev, lam_accel_dev);
+}
+
+int vp_sweep_adjoint_noalloc(vp_ctx* c, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,
+                             double* lam_accel_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (axis < 0 || axis > 5) return fail(VP_EINVAL, "axis must be 0..5");
+  if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
+  if (!f_in_dev || !lam_dev) return fail(VP_EINVAL, "null pointer");
+  const vp::SweepArgs a = sweep_args(c, axis, tau);
+  const bool want = axis >= 3 && lam_accel_dev;
+  if (want && a.nlines > VP_NOALLOC_MAX_LINES)
+    return fail(VP_EINVAL, "velocity sweep of %lld lines exceeds the %d-line device scratch of the "
+                           "allocation-free reverse sweep", a.nlines, VP_NOALLOC_MAX_LINES);
+  if (want && !c->scratch) return fail(VP_EHIP, "device scratch address not resolved");
+  // every line writes its own entry before the reduction reads it, so the
+  // scratch needs no clearing; no phase timing here (it would create events)
+  LAUNCH(c, vp::launch_sweep_adjoint(a, c->cfg.dtype, f_in_dev, lam_dev, want ? c->scratch : nullptr, c->stream));
+  if (want) {
+    const int l = axis - 3;
+    LAUNCH(c, vp::launch_reduce_lines(lam_accel_dev + (long long)l * c->np, c->scratch, c->np, a.nlines / c->np,
+                                      tau / c->dv[l], c->stream));
+  }
+  return VP_OK;
 }
 
 int vp_accel_adjoint(vp_ctx* c, const double* lam_accel_dev, void* lam_dev)
