@@ -73,6 +73,12 @@ struct vp_ctx {
   // workgroup sums of the x sweep (density without another pass over f);
   // null when the x sweep of this grid cannot produce them
   double* xsum = nullptr;
+  // per-velocity-cell line coefficients of the one-pass T_z T_y (null when
+  // the grid has no such pass)
+  void* dtab = nullptr;
+  // per-spatial-cell line coefficients of the kick passes (null when the
+  // velocity grid has none)
+  void* ktab = nullptr;
   // phase timing (vp_profile_*): pending event pairs per phase
   bool profiling = false;
   std::vector<hipEvent_t> ev_free;
@@ -221,6 +227,8 @@ void release(vp_ctx* c)
   for (auto& t : c->tw) hipFree(t);
   hipFree(c->part);
   hipFree(c->xsum);
+  hipFree(c->dtab);
+  hipFree(c->ktab);
   hipFree(c->red);
   hipFree(c->lphi);
   hipFree(c->radj);
@@ -482,6 +490,7 @@ int kick_n(vp_ctx* c, double tau, int reps)
   const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
   if (vp::kick_fused_supported(c->cfg.dtype, nv)) {
     vp::KickArgs a{};
+    a.tab = c->ktab;
     a.f = c->f;
     a.np = c->np;
     a.reps = reps;
@@ -496,6 +505,7 @@ int kick_n(vp_ctx* c, double tau, int reps)
   int r;
   if (vp::kick_pair_supported(c->cfg.dtype, nv)) {
     vp::KickArgs a{};
+    a.tab = c->ktab;
     a.f = c->f;
     a.np = c->np;
     a.reps = 1;
@@ -521,6 +531,7 @@ int kick_n(vp_ctx* c, double tau, int reps)
   }
   if (vp::kick_planes_supported(c->cfg.dtype, nv)) {   // T_vx | T_vy T_vz per half kick
     vp::KickArgs a{};
+    a.tab = c->ktab;
     a.f = c->f;
     a.np = c->np;
     a.reps = 1;
@@ -564,6 +575,7 @@ int drift(vp_ctx* c, double tau, bool x_sums = false)
     a.vmin_z = k.vmin[2];
     a.dv_z = c->dv[2];
     a.scale_z = tau / c->dx[2];
+    a.tab = c->dtab;
     {
       PhaseScope scope(c, 9);
       LAUNCH(c, vp::launch_drift_yz(a, k.dtype, c->stream));
@@ -697,6 +709,20 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
       release(c);
       return r;
     }
+  }
+  {
+    const int nv[3] = {cfg->nv[0], cfg->nv[1], cfg->nv[2]};
+    if ((vp::kick_fused_supported(cfg->dtype, nv) || vp::kick_pair_supported(cfg->dtype, nv) ||
+         vp::kick_planes_supported(cfg->dtype, nv)) &&
+        (r = dalloc(&c->ktab, vp::kick_table_bytes(cfg->dtype, c->np), "kick coefficients"))) {
+      release(c);
+      return r;
+    }
+  }
+  if (vp::drift_yz_supported(cfg->dtype, cfg->n[1], cfg->n[2], c->nv3) &&
+      (r = dalloc(&c->dtab, vp::drift_table_bytes(cfg->dtype, c->nv3), "drift coefficients"))) {
+    release(c);
+    return r;
   }
   hipError_t he = hipHostMalloc((void**)&c->host, sizeof(double) * 8, hipHostMallocDefault);
   if (he != hipSuccess) {
@@ -980,6 +1006,7 @@ int kick_to(vp_ctx* c, double tau, const void* src, void* dst, size_t fbytes)
   const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
   if (vp::kick_fused_supported(c->cfg.dtype, nv)) {
     vp::KickArgs a{};
+    a.tab = c->ktab;
     a.f = const_cast<void*>(src);
     a.out = dst;
     a.np = c->np;

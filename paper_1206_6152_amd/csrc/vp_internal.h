@@ -60,7 +60,11 @@ struct KickArgs {
   double scale[3];
   int reps;   // 1: one half kick; 2: two consecutive half kicks with the same acceleration
   void* out;  // one-pass kick only: write the result here (same layout) instead of over f
+  // per-spatial-cell line coefficients of the three velocity sweeps, filled by
+  // the launch functions before the pass: kick_table_bytes(dtype, np) bytes
+  void* tab;
 };
+size_t kick_table_bytes(int dtype, long long np);
 
 // True when a one-pass kernel exists for this velocity grid and element type.
 bool kick_fused_supported(int dtype, const int nv[3]);
@@ -89,7 +93,11 @@ struct DriftArgs {
   int periodic;
   double vmin_y, dv_y, scale_y;
   double vmin_z, dv_z, scale_z;
+  // per-velocity-cell line coefficients of the two sweeps, filled by
+  // launch_drift_yz before the pass: drift_table_bytes(dtype, nv3) bytes
+  void* tab;
 };
+size_t drift_table_bytes(int dtype, long long nv3);
 bool drift_yz_supported(int dtype, int ny, int nz, long long nv3);
 hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s);
 
