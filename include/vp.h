@@ -223,9 +223,11 @@ double vp_cell_self_integral(double dx, double dy, double dz);
  * recomputes one segment at a time; writes dL/df0 to grad_f0_dev (device,
  * layout and type of f, caller-owned, 16-byte aligned) and L to *loss_host.
  * On return f holds the final state and the context its acceleration, as after
- * vp_run(nsteps, dt). Allocates about (nsteps/ckpt_every + ckpt_every + 8)
- * copies of f for the call and frees them before returning (VP_ENOMEM if they
- * do not fit). Synchronises the stream. */
+ * vp_run(nsteps, dt). Allocates ceil(nsteps/ckpt_every) + ckpt_every + 1
+ * copies of f for the call (checkpoints, the states of one segment, and two
+ * arrays in which each step's sweep inputs are regenerated from the step's
+ * start), plus the acceleration of every step, and frees them before
+ * returning (VP_ENOMEM if they do not fit). Synchronises the stream. */
 int vp_sweep_adjoint(vp_ctx* ctx, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,
                      double* lam_accel_dev);
 int vp_accel_adjoint(vp_ctx* ctx, const double* lam_accel_dev, void* lam_dev);

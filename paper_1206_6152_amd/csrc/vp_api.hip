@@ -1026,7 +1026,27 @@ int kick_to(vp_ctx* c, double tau, const void* src, void* dst, size_t fbytes)
   return kick(c, tau);
 }
 
+// T_axis(tau) in place on the array at buf (left as c->f)
+int sweep_on(vp_ctx* c, int axis, double tau, void* buf)
+{
+  c->f = buf;
+  return sweep(c, axis, tau);
+}
+
 // Reverse mode of nsteps steps of Eq. (17) with checkpoints; see vp.h.
+//
+// Device memory: every k-th state of the forward run (ceil(nsteps/k) copies of
+// f), the other k-1 states of the segment being reversed, and two work arrays
+// in which the inputs of a step's nine sweeps are regenerated from the step's
+// start, in the order the reverse sweeps need them:
+//   closing half kick (a_{n+1}):  in8 = T_vy T_vx in6, then in7 = T_vx in6,
+//                                 with in6 = drift(kick(x0)) kept throughout;
+//   drift:                        in5 = T_y T_z in3, then in4 = T_z in3,
+//                                 with in3 = kick(x0) kept throughout;
+//   opening half kick (a_n):      in1 = T_vx x0 and in2 = T_vy in1.
+// Every regenerated input is computed by the kernels of the forward run, so it
+// is the forward input bit for bit; the price is twelve sweep passes per step
+// instead of eight.
 int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
 {
   const size_t fb = (size_t)c->np * (size_t)c->nv3 * (c->cfg.dtype == VP_F32 ? 4 : 8);
@@ -1034,19 +1054,17 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   const int nck = (nsteps + k - 1) / k;
   void* user_f = c->f;
   GradWork w{c};
-  // ck: every k-th state of the forward run; st[1..k-1]: the other states of one
-  // segment, recomputed; in[1..8]: the inputs of sweeps 1..8 of one step
-  std::vector<void*> ck(nck), st(k, nullptr), in(9, nullptr);
-  void* fin = nullptr;
+  // ck: every k-th state of the forward run; st[1..k-1]: the other states of
+  // one segment, recomputed; b1, b2: regenerated sweep inputs of one step
+  std::vector<void*> ck(nck), st(k, nullptr);
+  void *b1 = nullptr, *b2 = nullptr;
   double *ahist = nullptr, *lam_a = nullptr, *lam_p = nullptr;
   int r;
   for (int i = 0; i < nck; i++)
     if ((r = w.f(&ck[i], fb))) return r;
   for (int i = 1; i < k; i++)
     if ((r = w.f(&st[i], fb))) return r;
-  for (int i = 1; i < 9; i++)
-    if ((r = w.f(&in[i], fb))) return r;
-  if ((r = w.f(&fin, fb))) return r;
+  if ((r = w.f(&b1, fb)) || (r = w.f(&b2, fb))) return r;
   if ((r = w.d(&ahist, ab * (size_t)(nsteps + 1))) || (r = w.d(&lam_a, ab)) || (r = w.d(&lam_p, ab))) return r;
   auto A = [&](int n) { return ahist + (size_t)n * 3 * c->np; };
   auto set_accel = [&](int n) { return copy_f(c, c->accel, A(n), ab); };
@@ -1068,7 +1086,7 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
     closing = true;
   }
   if (closing && (r = kick(c, h))) return r;
-  if ((r = copy_f(c, fin, user_f, fb))) return r;
+  // user_f now holds the final state; the reverse pass leaves it alone
   // loss = -U of the final state, seed lam = dL/df = -dx^3 dv^3 phi(x)
   if ((r = potential_into(c, c->phi))) return r;
   const double dx3 = c->dx[0] * c->dx[1] * c->dx[2], dv3 = c->dv[0] * c->dv[1] * c->dv[2];
@@ -1077,7 +1095,6 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   LAUNCH(c, vp::launch_seed(lam, c->cfg.dtype, c->phi, c->ng, c->nv3, -dx3 * dv3, c->stream));
   HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
 
-  static const int axes[9] = {3, 4, 5, 2, 1, 0, 3, 4, 5};
   for (int seg = nck - 1; seg >= 0 && r == VP_OK; seg--) {
     const int s0 = seg * k, s1 = (s0 + k < nsteps) ? s0 + k : nsteps;
     st[0] = ck[seg];
@@ -1085,35 +1102,38 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
       if ((r = set_accel(n))) break;
       if ((r = kick_to(c, h, st[n - s0], st[n - s0 + 1], fb)) || (r = drift_accel(c, dt)) || (r = kick(c, h))) break;
     }
-    c->f = user_f;
     for (int n = s1 - 1; n >= s0 && r == VP_OK; n--) {
-      // inputs of the nine sweeps of step n, each sweep writing the next one's input
-      in[0] = st[n - s0];
-      if ((r = set_accel(n))) break;
-      for (int q = 0; q < 8 && r == VP_OK; q++) {
-        if (q == 6 && (r = set_accel(n + 1))) break;
-        r = sweep_to(c, axes[q], q >= 3 && q < 6 ? dt : h, in[q], in[q + 1]);
-      }
-      if (r) break;   // the stored acceleration is a_{n+1} from here
-      // second half kick (acceleration a_{n+1}), then a_{n+1} = A(state after the drift)
+      void* x0 = st[n - s0];
+      // closing half kick, acceleration a_{n+1}: in6 in b1, in8 then in7 in b2
+      if ((r = set_accel(n)) || (r = kick_to(c, h, x0, b1, fb))) break;
+      if ((r = drift(c, dt))) break;                                     // b1 = in6
+      if ((r = set_accel(n + 1)) || (r = sweep_to(c, 3, h, b1, b2)) || (r = sweep_on(c, 4, h, b2))) break;
       if ((r = copy_f(c, lam_a, lam_p, ab))) break;
-      for (int q = 8; q >= 6 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, in[q], lam, lam_a);
-      // the density adjoint's contribution to lam rides on the loads of the
-      // reverse x sweep that follows
-      if (r || (r = density_adjoint(c, lam_a))) break;
-      for (int q = 5; q >= 3 && r == VP_OK; q--)
-        r = sweep_adjoint(c, axes[q], dt, in[q], lam, nullptr, q == 5 ? c->radj : nullptr);
-      if (r) break;
-      if ((r = set_accel(n))) break;
+      if ((r = sweep_adjoint(c, 5, h, b2, lam, lam_a))) break;            // at in8
+      if ((r = sweep_to(c, 3, h, b1, b2)) || (r = sweep_adjoint(c, 4, h, b2, lam, lam_a))) break;   // at in7
+      if ((r = sweep_adjoint(c, 3, h, b1, lam, lam_a))) break;            // at in6
+      // a_{n+1} = A(state after the drift): the density adjoint's contribution
+      // to lam rides on the loads of the reverse x sweep that follows
+      if ((r = density_adjoint(c, lam_a))) break;
+      // drift: in3 in b1, in5 then in4 in b2
+      if ((r = set_accel(n)) || (r = kick_to(c, h, x0, b1, fb))) break;  // b1 = in3
+      if ((r = sweep_to(c, 2, dt, b1, b2)) || (r = sweep_on(c, 1, dt, b2))) break;   // b2 = in5
+      if ((r = sweep_adjoint(c, 0, dt, b2, lam, nullptr, c->radj))) break;
+      if ((r = sweep_to(c, 2, dt, b1, b2)) || (r = sweep_adjoint(c, 1, dt, b2, lam, nullptr))) break;   // at in4
+      if ((r = sweep_adjoint(c, 2, dt, b1, lam, nullptr))) break;         // at in3
+      // opening half kick, acceleration a_n: in1 in b1, in2 in b2
       HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
-      for (int q = 2; q >= 0 && r == VP_OK; q--) r = sweep_adjoint(c, axes[q], h, in[q], lam, lam_p);
+      if ((r = sweep_to(c, 3, h, x0, b1)) || (r = sweep_to(c, 4, h, b1, b2))) break;
+      if ((r = sweep_adjoint(c, 5, h, b2, lam, lam_p)) || (r = sweep_adjoint(c, 4, h, b1, lam, lam_p)) ||
+          (r = sweep_adjoint(c, 3, h, x0, lam, lam_p)))
+        break;
     }
   }
   c->f = user_f;
   if (r) return r;
   // a_0 = A(f0)
   if ((r = accel_adjoint(c, lam_p, lam))) return r;
-  if ((r = copy_f(c, user_f, fin, fb)) || (r = set_accel(nsteps))) return r;
+  if ((r = set_accel(nsteps))) return r;
   HIP_TRY(hipStreamSynchronize(c->stream));
   *loss = -c->host[0];
   return VP_OK;

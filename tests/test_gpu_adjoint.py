@@ -246,3 +246,56 @@ def test_grad_same_bits_for_every_checkpoint_interval(bc, dtype):
         assert L == outs[0][0]
         assert np.array_equal(g, outs[0][1])
         assert np.array_equal(fin, outs[0][2])
+
+
+def test_benchmark_grid_gradient_fp32_against_fp64_and_finite_differences():
+    # The reverse mode on the benchmark's grid (32^3 x 32^3, 1.07e9 cells) for 10
+    # steps with checkpoints every 5: the call holds ceil(10/5) + 5 + 1 = 8 copies
+    # of f (34 GB in FP32, 69 GB in FP64). The FP32 gradient with respect to the
+    # initial density contrast is compared with the FP64 one, and both with
+    # central differences of the FP64 forward map along the perturbation's own
+    # mode and along random unit directions.
+    torch = _t()
+    from paper_1206_6152_amd.autograd import field_energy, initial_f
+    w = inputs.jeans_32_32()
+    steps, ckpt = 10, 5
+    dens, m = inputs.separable_factors(w)
+    delta = _dev(dens - 1.0).requires_grad_(True)
+    m_v = _dev(m)
+    grads = {}
+    for dtype in (VP_F64, VP_F32):
+        L = field_energy(delta, m_v, w, dtype, steps, w.dt, ckpt)
+        L.backward()
+        grads[dtype] = (float(L.detach()), delta.grad.detach().clone())
+        delta.grad = None
+        torch.cuda.empty_cache()
+    (L64, g64), (L32, g32) = grads[VP_F64], grads[VP_F32]
+    r32 = float((g32 - g64).abs().sum() / g64.abs().sum())
+    print("L64 %.12e L32 %.12e, FP32 vs FP64 gradient rel L1 %.2e" % (L64, L32, r32), flush=True)
+    assert L32 == pytest.approx(L64, rel=1e-4)
+    assert r32 <= 1e-3
+
+    def loss_at(d):
+        f = initial_f(d, m_v, 1.0, torch.float64)
+        sim = Simulator(config_of(w, VP_F64), f)
+        sim.run(steps, w.dt)
+        e = sim.energy()
+        sim.close()
+        del f
+        return -e[1]
+
+    rng = np.random.default_rng(32)
+    mode = (dens - 1.0) / np.linalg.norm(dens - 1.0)
+    dirs = [("cosine mode", mode)]
+    for i in range(3):
+        d = rng.standard_normal(w.n)
+        dirs.append(("random unit %d" % i, d / np.linalg.norm(d)))
+    eps = 1e-4
+    for name, d in dirs:
+        d = _dev(d)
+        fd = (loss_at(delta.detach() + eps * d) - loss_at(delta.detach() - eps * d)) / (2 * eps)
+        a64, a32 = float((g64 * d).sum()), float((g32 * d).sum())
+        print("%s: FD %.10e  FP64 adjoint %.10e (%.2e)  FP32 adjoint %.10e (%.2e)" % (
+            name, fd, a64, abs(a64 - fd) / abs(fd), a32, abs(a32 - fd) / abs(fd)), flush=True)
+        assert abs(a64 - fd) <= 1e-4 * abs(fd)
+        assert abs(a32 - fd) <= 1e-3 * abs(fd)
