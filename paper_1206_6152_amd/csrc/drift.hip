@@ -77,7 +77,14 @@ __global__ __launch_bounds__(256) void drift_table_kernel(DriftArgs a)
   yt[j] = LineTab<T>{cy.alpha, cy.c1, cy.c2, (cy.shift & 0xffff) | flags};
 }
 
-template <typename T, int NY, int NZ, int W, int TILES>
+// Chunks narrower than a 128-byte cache line (W sizeof(T) = 128 / G bytes,
+// the 48-cell planes) share each line among G consecutive chunks. A
+// unit is then G workgroups that take chunks (c TILES + t) G + q, q = 0..G-1,
+// tile by tile; with a.xcd_group the G workgroups of a unit are b = 8 (G m +
+// q) + x, which the round-robin over the 8 XCDs places on one XCD (x) one
+// after another, so that the halves or quarters of each line meet in that
+// XCD's L2 instead of being fetched from HBM once per chunk.
+template <typename T, int NY, int NZ, int W, int TILES, int G>
 __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_block(DriftArgs a)
 {
   using S = DriftShape<T, NY, NZ, W>;
@@ -85,14 +92,27 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
   __shared__ T L[S::ELEMS];
   const int tid = threadIdx.x;
   const long long nchunk = a.nv3 / W;
-  const long long jc0 = (long long)blockIdx.x * TILES;
+  const long long upx = (nchunk / G + TILES - 1) / TILES;   // units per x index
+  long long unit;
+  int q;
+  if (G > 1 && a.xcd_group) {
+    const long long b = blockIdx.x, x = b & 7, k = b >> 3;
+    q = (int)(k % G);
+    unit = 8 * (k / G) + x;
+  } else {
+    q = (int)(blockIdx.x % G);
+    unit = blockIdx.x / G;
+  }
+  const long long ix = unit / upx, cg = unit - ix * upx;
+  auto chunk = [&](int t) { return (cg * TILES + t) * G + q; };
+  const long long jc0 = chunk(0);
   const bool periodic = a.periodic != 0;
   const LineTab<T>* zt = static_cast<const LineTab<T>*>(a.tab);
   const LineTab<T>* yt = zt + a.nv3;
   // z-line lane (iy, w), y-line lane (iz, w): the same split of the lane index
   const int i0 = tid / W, w = tid - i0 * W;
   const unsigned RB = (unsigned)(a.nv3 * (long long)sizeof(T));   // bytes from one z to the next
-  const char* slab = static_cast<const char*>(a.f) + (long long)blockIdx.y * NY * NZ * a.nv3 * (long long)sizeof(T);
+  const char* slab = static_cast<const char*>(a.f) + ix * NY * NZ * a.nv3 * (long long)sizeof(T);
   const unsigned zoff = (unsigned)i0 * (unsigned)NZ * RB + (unsigned)w * (unsigned)sizeof(T);
   auto tile = [&](long long jc) { return slab + jc * W * (long long)sizeof(T); };
   T v[NZ];
@@ -103,8 +123,8 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
   }
 #pragma unroll
   for (int k = 0; k < TILES; k++) {
-    const long long jc = jc0 + k;
-    if (jc >= nchunk) break;                      // uniform over the workgroup
+    const long long jc = chunk(k);
+    if (jc >= nchunk) break;                      // uniform over the workgroup (ragged ends: G = 1)
     if (tid < S::LZ) {
       // the z line, mirrored where vz < 0, takes the forward update and is
       // parked in LDS in that order, at its y place in the y sweep's
@@ -123,8 +143,8 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
     }
     __syncthreads();
     // the next tile's z lines go into flight before this tile's y lines
-    if (k + 1 < TILES && jc + 1 < nchunk && tid < S::LZ) {
-      const char* src = tile(jc + 1);
+    if (k + 1 < TILES && chunk(k + 1) < nchunk && tid < S::LZ) {
+      const char* src = tile(chunk(k + 1));
 #pragma unroll
       for (int r = 0; r < NZ; r++) v[r] = *reinterpret_cast<const T*>(src + (size_t)r * RB + zoff);
     }
@@ -153,34 +173,63 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
 }
 
 template <typename T, int NP, int W, int TILES>
-hipError_t launch_drift_yz_sq(const DriftArgs& a, hipStream_t s)
+hipError_t launch_drift_yz_sq(const DriftArgs& a0, hipStream_t s)
 {
   using S = DriftShape<T, NP, NP, W>;
   static_assert(S::fits, "tile does not fit the LDS");
-  const long long nchunk = a.nv3 / W;
-  if (a.nx <= 0 || nchunk <= 0) return hipSuccess;
-  hipLaunchKernelGGL((drift_table_kernel<T, NP, NP>), dim3((unsigned)((a.nv3 + 255) / 256)), dim3(256), 0, s, a);
+  constexpr int G = (W * (int)sizeof(T) >= 128) ? 1 : 128 / (W * (int)sizeof(T));
+  const long long nchunk = a0.nv3 / W;
+  if (a0.nx <= 0 || nchunk <= 0) return hipSuccess;
+  if (G > 1 && nchunk % (TILES * G) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((drift_table_kernel<T, NP, NP>), dim3((unsigned)((a0.nv3 + 255) / 256)), dim3(256), 0, s, a0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long groups = (nchunk + TILES - 1) / TILES;
-  hipLaunchKernelGGL((drift_yz_block<T, NP, NP, W, TILES>), dim3((unsigned)groups, (unsigned)a.nx), dim3(S::THREADS),
-                     0, s, a);
+  const long long units = a0.nx * ((nchunk / G + TILES - 1) / TILES);
+  DriftArgs a = a0;
+  a.xcd_group = (G > 1 && units % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((drift_yz_block<T, NP, NP, W, TILES, G>), dim3((unsigned)(units * G)), dim3(S::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
 // (y, z) planes of 16, 24 or 32 cells with whole-cache-line velocity chunks
-static int drift_yz_width(int dtype, int ny, int nz, long long nv3)
+// Velocity cells per chunk (W), tiles per workgroup, and chunks per cache
+// line (G) of the one-pass T_z T_y: whole-line chunks up to 32-cell planes;
+// 48-cell planes take half-line chunks (FP32 16 cells, FP64 8), whose
+// workgroups are grouped per line (above). 64-cell planes would take quarter
+// lines (32 bytes); measured on the 16 x 64 x 64 slab, that pass took 2.7
+// times a plain sweep, so those planes keep two plain sweeps.
+struct DriftPlan {
+  int w, tiles, g;
+};
+
+static DriftPlan drift_plan(int dtype, int ny, int nz, long long nv3)
 {
-  if (ny != nz) return 0;
-  int w = 0;
-  if (dtype == 0) w = (ny == 16) ? 64 : (ny == 24 || ny == 32) ? 32 : 0;
-  else w = (ny == 16) ? 32 : (ny == 24 || ny == 32) ? 16 : 0;
-  if (w == 0 || nv3 % w != 0) return 0;
-  // 32-bit byte offsets within a tile, and x indices on the grid's y dimension
-  if ((long long)ny * nz * nv3 * (dtype == 0 ? 4 : 8) >= (1LL << 32)) return 0;
-  return w;
+  DriftPlan p{0, 0, 1};
+  if (ny != nz) return p;
+  const int es = dtype == 0 ? 4 : 8;
+  if (dtype == 0) {
+    switch (ny) {
+      case 16: p = {64, 4, 1}; break;
+      case 24: case 32: p = {32, 4, 1}; break;
+      case 48: p = {16, 4, 2}; break;
+      default: return DriftPlan{0, 0, 1};
+    }
+  } else {
+    switch (ny) {
+      case 16: p = {32, 2, 1}; break;
+      case 24: p = {16, 2, 1}; break;
+      case 32: p = {16, 4, 1}; break;
+      case 48: p = {8, 2, 2}; break;
+      default: return DriftPlan{0, 0, 1};
+    }
+  }
+  if (nv3 % p.w != 0) return DriftPlan{0, 0, 1};
+  if (p.g > 1 && (nv3 / p.w) % (p.tiles * p.g) != 0) return DriftPlan{0, 0, 1};
+  // 32-bit byte offsets within a tile: the largest is under the tile's span
+  if (((long long)ny * nz * nv3 - nv3 + p.w) * es >= (1LL << 32)) return DriftPlan{0, 0, 1};
+  return p;
 }
 
 size_t drift_table_bytes(int dtype, long long nv3)
@@ -188,19 +237,20 @@ size_t drift_table_bytes(int dtype, long long nv3)
   return (size_t)(2 * nv3) * (dtype == 0 ? sizeof(LineTab<float>) : sizeof(LineTab<double>));
 }
 
-bool drift_yz_supported(int dtype, int ny, int nz, long long nv3) { return drift_yz_width(dtype, ny, nz, nv3) != 0; }
+bool drift_yz_supported(int dtype, int ny, int nz, long long nv3) { return drift_plan(dtype, ny, nz, nv3).w != 0; }
 
 // Tiles per workgroup: four, except two for the FP64 16- and 24-planes, whose
-// workgroups are small enough that several share a CU anyway.
+// workgroups are small enough that several share a CU anyway, and for the
+// FP64 48-planes.
 hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
 {
-  const int w = drift_yz_width(dtype, a.ny, a.nz, a.nv3);
-  if (!a.tab || a.nx > 65535) return hipErrorInvalidValue;
+  if (!a.tab || drift_plan(dtype, a.ny, a.nz, a.nv3).w == 0) return hipErrorInvalidValue;
   if (dtype == 0) {
     switch (a.ny) {
       case 16: return launch_drift_yz_sq<float, 16, 64, 4>(a, s);
       case 24: return launch_drift_yz_sq<float, 24, 32, 4>(a, s);
       case 32: return launch_drift_yz_sq<float, 32, 32, 4>(a, s);
+      case 48: return launch_drift_yz_sq<float, 48, 16, 4>(a, s);
       default: break;
     }
   } else {
@@ -208,10 +258,10 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
       case 16: return launch_drift_yz_sq<double, 16, 32, 2>(a, s);
       case 24: return launch_drift_yz_sq<double, 24, 16, 2>(a, s);
       case 32: return launch_drift_yz_sq<double, 32, 16, 4>(a, s);
+      case 48: return launch_drift_yz_sq<double, 48, 8, 2>(a, s);
       default: break;
     }
   }
-  (void)w;
   return hipErrorInvalidValue;
 }
 }  // namespace vp

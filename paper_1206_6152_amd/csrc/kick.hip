@@ -262,8 +262,23 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
   constexpr int CH = S::CH;
   __shared__ T L[S::ELEMS];
   const int tid = threadIdx.x;
-  const long long s = blockIdx.x / S::NCH;
-  const int c0 = (int)(blockIdx.x - s * S::NCH) * CH;
+  // workgroup -> (spatial cell s, slice): the slices of one velocity block
+  // take consecutive workgroups, or with a.xcd_group (np a multiple of 8) the
+  // workgroups b = 8 (NCH m + q) + x, which the hardware's round-robin over
+  // the 8 XCDs places on one XCD (x) one after another, so that slices that
+  // share cache lines (vz-slices: runs of CH values of each vz row) meet in
+  // that XCD's L2
+  long long s;
+  int slice;
+  if (a.xcd_group) {
+    const long long b = blockIdx.x, x = b & 7, k = b >> 3, m = k / S::NCH;
+    slice = (int)(k - m * S::NCH);
+    s = 8 * m + x;
+  } else {
+    s = blockIdx.x / S::NCH;
+    slice = (int)(blockIdx.x - s * S::NCH);
+  }
+  const int c0 = slice * CH;
   const long long cofs = PASS == 0 ? c0 : (PASS == 1 ? c0 * NV : c0 * NV * NV);
   T* g = static_cast<T*>(a.f) + s * (long long)(NV * NV * NV) + cofs;
   // the two sweeps: axis A then axis B (0 = vx, 1 = vy, 2 = vz)
@@ -390,6 +405,40 @@ hipError_t launch_kick_pair_cube(const KickArgs& a, int pass, hipStream_t s)
   return hipGetLastError();
 }
 
+// The three two-sweep passes of two consecutive half kicks (T_vx T_vy on
+// slices of CV vz-planes, T_vz T_vx on slices of CY vy-rows, T_vy T_vz on
+// slices of CX vx-planes) for velocity blocks whose halves exceed the LDS:
+// six sweeps in three passes instead of four (two T_vx sweeps and two
+// plane passes)
+template <typename T, int NV, int CV, int CY, int CX>
+hipError_t launch_kick_slices(const KickArgs& a0, int pass, hipStream_t s)
+{
+  static_assert(PairShape<T, NV, 0, CV>::fits && PairShape<T, NV, 1, CY>::fits && PairShape<T, NV, 2, CX>::fits,
+                "slice does not fit the LDS");
+  if (a0.np <= 0) return hipSuccess;
+  if (pass == 0) {
+    const hipError_t e = launch_kick_table<T, NV>(a0, s);
+    if (e != hipSuccess) return e;
+  }
+  KickArgs a = a0;
+  a.xcd_group = (a.np % 8 == 0) ? 1 : 0;
+  switch (pass) {
+    case 0:
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 0, CV>), dim3((unsigned)(PairShape<T, NV, 0, CV>::NCH * a.np)),
+                         dim3(PairShape<T, NV, 0, CV>::THREADS), 0, s, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 1, CY>), dim3((unsigned)(PairShape<T, NV, 1, CY>::NCH * a.np)),
+                         dim3(PairShape<T, NV, 1, CY>::THREADS), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((kick_pair_block<T, NV, 2, CX>), dim3((unsigned)(PairShape<T, NV, 2, CX>::NCH * a.np)),
+                         dim3(PairShape<T, NV, 2, CX>::THREADS), 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
 // T_vy then T_vz on slices of CH whole (vy, vz) planes (one slice per
 // workgroup): for velocity blocks too large for the half-block passes
 template <typename T, int NV, int CH>
@@ -439,6 +488,21 @@ hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hip
   if (!kick_planes_supported(dtype, nv)) return hipErrorInvalidValue;
   if (dtype == 0) return nv[0] == 48 ? launch_kick_planes<float, 48, 12>(a, s) : launch_kick_planes<float, 64, 8>(a, s);
   return nv[0] == 48 ? launch_kick_planes<double, 48, 6>(a, s) : launch_kick_planes<double, 64, 4>(a, s);
+}
+
+// 48^3 and 64^3 FP32 blocks: vz-slices of 16 and 8 planes, vy-slices of 16
+// and 8 rows, vx-slices of 12 and 8 planes (147, 150, 110 KiB; 128, 130,
+// 130 KiB)
+bool kick_slices_supported(int dtype, const int nv[3])
+{
+  return dtype == 0 && nv[0] == nv[1] && nv[1] == nv[2] && (nv[0] == 48 || nv[0] == 64);
+}
+
+hipError_t launch_kick_slices(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)
+{
+  if (!kick_slices_supported(dtype, nv) || pass < 0 || pass > 2) return hipErrorInvalidValue;
+  return nv[0] == 48 ? launch_kick_slices<float, 48, 16, 16, 12>(a, pass, s)
+                     : launch_kick_slices<float, 64, 8, 8, 8>(a, pass, s);
 }
 
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)

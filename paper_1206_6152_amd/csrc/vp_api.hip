@@ -539,6 +539,13 @@ int kick_n(vp_ctx* c, double tau, int reps)
       a.a[l] = c->accel + (long long)l * c->np;
       a.scale[l] = tau / c->dv[l];
     }
+    if (reps == 2 && vp::kick_slices_supported(c->cfg.dtype, nv)) {   // T_vx T_vy | T_vz T_vx | T_vy T_vz
+      for (int pass = 0; pass < 3; pass++) {
+        PhaseScope scope(c, 12);
+        LAUNCH(c, vp::launch_kick_slices(a, c->cfg.dtype, nv, pass, c->stream));
+      }
+      return VP_OK;
+    }
     for (int i = 0; i < reps; i++) {
       if ((r = sweep(c, 3, tau))) return r;
       PhaseScope scope(c, 12);

@@ -63,6 +63,7 @@ struct KickArgs {
   // per-spatial-cell line coefficients of the three velocity sweeps, filled by
   // the launch functions before the pass: kick_table_bytes(dtype, np) bytes
   void* tab;
+  int xcd_group;  // set by the launch functions: slices of one block on one XCD
 };
 size_t kick_table_bytes(int dtype, long long np);
 
@@ -75,6 +76,11 @@ hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_
 // T_vx T_vz, pass 2 = T_vz T_vy (rightmost first). A half kick is pass 0 and a
 // T_vz sweep; two half kicks in a row are passes 0, 1, 2.
 bool kick_pair_supported(int dtype, const int nv[3]);
+// The six sweeps of two consecutive half kicks in three passes over slices
+// (T_vx T_vy on vz-slices, T_vz T_vx on vy-slices, T_vy T_vz on vx-slices),
+// for FP32 48^3 and 64^3 blocks; pass 0 also fills the coefficient table.
+bool kick_slices_supported(int dtype, const int nv[3]);
+hipError_t launch_kick_slices(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
 // T_vy then T_vz in one pass over slices of whole (vy, vz) planes, for
 // velocity blocks too large for the passes above (48^3 and 64^3: 12 and 8
@@ -96,6 +102,7 @@ struct DriftArgs {
   // per-velocity-cell line coefficients of the two sweeps, filled by
   // launch_drift_yz before the pass: drift_table_bytes(dtype, nv3) bytes
   void* tab;
+  int xcd_group;  // set by launch_drift_yz: chunks that share cache lines on one XCD
 };
 size_t drift_table_bytes(int dtype, long long nv3);
 bool drift_yz_supported(int dtype, int ny, int nz, long long nv3);

@@ -101,7 +101,7 @@ def test_drift_equals_three_sweeps_and_oracle(bc, dtype):
 
 
 @pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
-@pytest.mark.parametrize("plane", [16, 24, 32])
+@pytest.mark.parametrize("plane", [16, 24, 32, 48, 64])
 @pytest.mark.parametrize("nu_max", [0.7, 2.4])
 @pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
 def test_one_pass_drift_planes(plane, dtype, nu_max, bc):
@@ -135,7 +135,7 @@ def test_one_pass_drift_planes(plane, dtype, nu_max, bc):
 @pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
 @pytest.mark.parametrize("shape", [((4, 16, 16), (16, 16, 16)), ((2, 6, 4), (8, 8, 8)), ((2, 3, 4), (8, 12, 16)),
                                    ((2, 2, 4), (32, 32, 32)), ((2, 2, 2), (48, 48, 48)),
-                                   ((2, 2, 2), (64, 64, 64))])
+                                   ((2, 2, 2), (64, 64, 64)), ((1, 2, 3), (48, 48, 48))])
 def test_run_equals_repeated_steps(shape, dtype):
     # vp_run merges the closing and opening half kicks of consecutive steps;
     # the result must be the same bits as separate vp_step calls
@@ -165,13 +165,17 @@ def test_run_equals_repeated_steps(shape, dtype):
 @pytest.mark.parametrize("dtype,plane,nx,nv", [(VP_F32, 16, 48, (8, 8, 16)), (VP_F32, 24, 32, (8, 8, 16)),
                                                 (VP_F32, 32, 12, (8, 8, 16)), (VP_F32, 32, 3, (2, 3, 16)),
                                                 (VP_F32, 16, 1, (1, 3, 64)), (VP_F64, 32, 3, (1, 3, 16)),
-                                                (VP_F64, 24, 1, (1, 3, 16)), (VP_F64, 16, 3, (1, 3, 32))])
+                                                (VP_F64, 24, 1, (1, 3, 16)), (VP_F64, 16, 3, (1, 3, 32)),
+                                                (VP_F32, 48, 8, (4, 4, 8)), (VP_F32, 64, 8, (2, 4, 16)),
+                                                (VP_F64, 48, 2, (4, 4, 8)), (VP_F64, 64, 2, (2, 4, 16))])
 def test_one_pass_drift_many_tiles_per_workgroup(dtype, plane, nx, nv):
     # a workgroup walks several (x, velocity chunk) tiles (four, or two for
     # FP64 planes of 16 and 24) and loads the next one while it sweeps the
     # current one; the tile counts here include ragged ends (9 and 3 tiles in
-    # FP32; 9, 3 and
-    # 9 in FP64)
+    # FP32; 9, 3 and 9 in FP64). The 48-planes take chunks narrower than a
+    # cache line, and these cases have a multiple of 8 workgroup units, so the
+    # workgroups that share lines are grouped per XCD (64-planes keep two
+    # plain sweeps; their cases check that route).
     print("case", dtype, plane, nx, nv, flush=True)
     w = small_workload(VP_BC_PERIODIC, n=(nx, plane, plane), nv=nv)
     w = w.__class__(name="d", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
