@@ -1,7 +1,7 @@
 // kick.hip -- the velocity half kicks of Eq. (17) (T_vx, T_vy, T_vz with the
 // acceleration of each spatial cell; Sec. 2.1 of Yoshikawa, Yoshida &
-// Umemura) in passes that hold a whole velocity block, half of one, or
-// slices of whole planes on chip. The line update is that of sweep.hip
+// Umemura) in passes that hold a whole velocity block or slices of one on
+// chip. The line update is that of sweep.hip
 // (pfc_line.h), so every pass rounds like the single sweeps. gfx950.
 #include "vp_internal.h"
 
@@ -200,18 +200,16 @@ hipError_t launch_kick_cube(const KickArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
-// ---- two velocity sweeps in one pass over half a velocity block --------------
-// When a whole velocity block does not fit in LDS but half of it does (FP64
-// 32^3: 256 KiB, half 128 KiB), two consecutive sweeps whose lines both lie in
-// the half run in one pass: PASS 0 is T_vx then T_vy on the half with vz in
-// [c0, c0 + CH); PASS 1 is T_vz then T_vx on the half with vy in the chunk;
-// PASS 2 is T_vy then T_vz on the half with vx in the chunk. A half kick is
-// PASS 0 and a T_vz sweep; the two half kicks between two drifts (T_vx T_vy
-// T_vz T_vx T_vy T_vz) are PASS 0, 1, 2. Each LDS layout keeps the HBM-
-// contiguous axis contiguous and pads rows so both sweep directions are
-// bank-conflict free; the arithmetic is that of the single sweeps. With CH
-// below NV / 2 the same kernel takes slices of CH planes (PASS 2 only, for
-// blocks whose half does not fit either).
+// ---- two velocity sweeps in one pass over slices of a velocity block ---------
+// When a whole velocity block does not fit in LDS, two consecutive sweeps whose
+// lines both lie in a slice of CH planes run in one pass: PASS 0 is T_vx then
+// T_vy on the slice with vz in [c0, c0 + CH); PASS 1 is T_vz then T_vx on the
+// slice with vy in the chunk; PASS 2 is T_vy then T_vz on the slice with vx in
+// the chunk. The two half kicks between two drifts (T_vx T_vy T_vz T_vx T_vy
+// T_vz) are PASS 0, 1, 2; a lone half kick is a T_vx sweep and PASS 2 (or
+// PASS 0 and a T_vz sweep). Each LDS layout keeps the HBM-contiguous axis
+// contiguous and pads rows so both sweep directions are bank-conflict free;
+// the arithmetic is that of the single sweeps.
 template <typename T, int NV, int PASS, int CH_ = NV / 2>
 struct PairShape {
   static constexpr int CH = CH_;                         // planes across the third axis
@@ -381,30 +379,6 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
   }
 }
 
-template <typename T, int NV>
-hipError_t launch_kick_pair_cube(const KickArgs& a, int pass, hipStream_t s)
-{
-  if (a.np <= 0) return hipSuccess;
-  const hipError_t e = launch_kick_table<T, NV>(a, s);
-  if (e != hipSuccess) return e;
-  const unsigned blocks = (unsigned)(2 * a.np);
-  switch (pass) {
-    case 0:
-      static_assert(PairShape<T, NV, 0>::fits, "half block does not fit the LDS");
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 0, NV / 2>), dim3(blocks), dim3(PairShape<T, NV, 0>::THREADS), 0, s, a);
-      break;
-    case 1:
-      static_assert(PairShape<T, NV, 1>::fits, "half block does not fit the LDS");
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 1, NV / 2>), dim3(blocks), dim3(PairShape<T, NV, 1>::THREADS), 0, s, a);
-      break;
-    default:
-      static_assert(PairShape<T, NV, 2>::fits, "half block does not fit the LDS");
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 2, NV / 2>), dim3(blocks), dim3(PairShape<T, NV, 2>::THREADS), 0, s, a);
-      break;
-  }
-  return hipGetLastError();
-}
-
 // The three two-sweep passes of two consecutive half kicks (T_vx T_vy on
 // slices of CV vz-planes, T_vz T_vx on slices of CY vy-rows, T_vy T_vz on
 // slices of CX vx-planes) for velocity blocks whose halves exceed the LDS:
@@ -505,10 +479,13 @@ hipError_t launch_kick_slices(const KickArgs& a, int dtype, const int nv[3], int
                      : launch_kick_slices<float, 64, 8, 8, 8>(a, pass, s);
 }
 
+// FP64 32^3 blocks: quarter-block slices (8 planes or rows, 66 KiB), two
+// workgroups per CU, the vz-slices grouped per XCD (3.05 ms per pass on the
+// 32^3 x 32^3 grid, against 3.25 for half blocks with one workgroup per CU)
 hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)
 {
   if (!kick_pair_supported(dtype, nv) || pass < 0 || pass > 2) return hipErrorInvalidValue;
-  return launch_kick_pair_cube<double, 32>(a, pass, s);
+  return launch_kick_slices<double, 32, 8, 8, 8>(a, pass, s);
 }
 
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)

@@ -71,10 +71,12 @@ size_t kick_table_bytes(int dtype, long long np);
 bool kick_fused_supported(int dtype, const int nv[3]);
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
 
-// Two consecutive velocity sweeps in one pass over half velocity blocks (the
-// whole block does not fit on chip, half does): pass 0 = T_vy T_vx, pass 1 =
-// T_vx T_vz, pass 2 = T_vz T_vy (rightmost first). A half kick is pass 0 and a
-// T_vz sweep; two half kicks in a row are passes 0, 1, 2.
+// Two consecutive velocity sweeps in one pass over slices of FP64 32^3
+// velocity blocks (the whole block does not fit on chip): pass 0 = T_vy T_vx
+// on vz-slices, pass 1 = T_vx T_vz on vy-slices, pass 2 = T_vz T_vy on
+// vx-slices (rightmost first), each slice a quarter block. A half kick is
+// pass 0 and a T_vz sweep; two half kicks in a row are passes 0, 1, 2. Pass 0
+// also fills the coefficient table.
 bool kick_pair_supported(int dtype, const int nv[3]);
 // The six sweeps of two consecutive half kicks in three passes over slices
 // (T_vx T_vy on vz-slices, T_vz T_vx on vy-slices, T_vy T_vz on vx-slices),
