@@ -124,6 +124,18 @@ def committed_traffic(w, elem_bytes, kernel):
     return traffic.get(kernel)
 
 
+WORKLOAD_TEXT = {
+    "jeans_32x32": "Jeans instability: periodic unit cube, G=rho0=1, k/k_J=0.5, A=0.01 cosine along x on a "
+                   "Maxwellian, v in [-5s,5s]^3",
+    "landau_8x16": "gravitational Landau damping: periodic unit cube, G=rho0=1, k/k_J=2, A=0.05 cosine along x on a "
+                   "Maxwellian, v in [-5s,5s]^3",
+    "king_w6_48x48": "isolated King sphere W0=6 (G=sigma=r0=1), box +-r_t, velocities within the central escape "
+                     "speed, doubled-grid Poisson",
+    "slab_16x64x64_64": "one GPU's 16x64x64 slab of a 64^3 periodic box, Maxwellian (k_J=16 pi) times a Gaussian "
+                        "random density field (P(k)~k^-2, rms 0.02, seed 1206), v in [-1,1]^3",
+    "jeans_adjoint_16x24": "Jeans set-up with a per-cell Gaussian density perturbation (rms 1e-3, seed 6152)",
+}
+
 PHASE_KERNEL = {
     "kick": "one-pass half kick (T_vx, T_vy, T_vz of each velocity block)",
     "kick2": "one-pass pair of half kicks (two T_vz T_vy T_vx with one acceleration)",
@@ -157,11 +169,14 @@ def kernel_name(phase, w, elem_bytes):
     if phase in ("kick", "kick2"):
         return "vp::kick_block<%s, %d, %d, %d, %d>" % (t, w.nv[0], w.nv[1], w.nv[2], 2 if phase == "kick2" else 1)
     if phase == "kick_pair":
+        if elem_bytes == 8 and w.nv[0] == 32:
+            return "vp::kick_pair_block<double, 32, 0, 8>"   # first of the three quarter-block passes
         return "vp::kick_pair_block<%s, %d, 2, %d>" % (t, w.nv[0], plane_slices(w, elem_bytes))
     if phase == "drift_yz":
-        wd = {16: 64, 24: 32, 32: 32}[w.n[1]] if elem_bytes == 4 else {16: 32, 24: 16, 32: 16}[w.n[1]]
-        tiles = 4 if elem_bytes == 4 or w.n[1] == 32 else 2      # tiles per workgroup
-        return "vp::drift_yz_block<%s, %d, %d, %d, %d>" % (t, w.n[1], w.n[2], wd, tiles)
+        # (velocity cells per chunk, tiles per workgroup, chunks per cache line)
+        plan = ({16: (64, 4, 1), 24: (32, 4, 1), 32: (32, 4, 1), 48: (16, 4, 2)} if elem_bytes == 4 else
+                {16: (32, 2, 1), 24: (16, 2, 1), 32: (16, 4, 1), 48: (8, 2, 2)})[w.n[1]]
+        return "vp::drift_yz_block<%s, %d, %d, %d, %d, %d>" % ((t, w.n[1], w.n[2]) + plan)
     axis = ["x", "y", "z", "vx", "vy", "vz"].index(phase)
     n = (list(w.n) + list(w.nv))[axis]
     if axis == 5:
@@ -407,10 +422,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": w.name,
-            "description": "periodic unit cube, G=rho0=1, k/k_J=0.5, A=0.01 cosine along x on a "
-                           "Maxwellian, v in [-5s,5s]^3, %s spatial x %s velocity cells, fixed dt=%.6g; "
-                           "f stored/swept in FP32, density/Poisson/acceleration FP64"
-                           % ("x".join(map(str, w.n)), "x".join(map(str, w.nv)), w.dt),
+            "description": "%s; %s spatial x %s velocity cells, %s; f stored/swept in FP32, "
+                           "density/Poisson/acceleration FP64"
+                           % (WORKLOAD_TEXT.get(w.name, w.name), "x".join(map(str, w.n)), "x".join(map(str, w.nv)),
+                              "fixed dt=%.6g" % w.dt if w.dt > 0 else "the Courant step (C=0.5) of the initial state"),
             "cells": w.cells,
             "sweeps_per_step": 9,
             "parallelism": "single GPU",
