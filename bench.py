@@ -33,10 +33,10 @@ PEAK_HBM_GBPS = 8000.0   # MI355X HBM3E, AMD public specification
 # Vector ALU issue rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # lane-operations/s (= 157.3 TFLOP/s FP32 / 2 for FMA / 2 for packed pairs).
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Arithmetic of one cell in one sweep: line maximum (1), f_{k+1} - f_k (1), 2 f_k (1),
-# 2 f_k - 2 f_inf (1), two clamps (2), q_k = fma(c2, Lm, fma(c1, Lp, f_k)) (2),
-# q_{k-1} - q_k (1), g_k = fma(alpha, q_{k-1} - q_k, f_k) (1).
-OPS_PER_CELL_SWEEP = 10
+# Arithmetic of one cell in one sweep: line maximum (a max3 covers two cells: 0.5),
+# f_{k+1} - f_k (1), 2 f_k (1), 2 f_inf - 2 f_k (1), two clamps (2),
+# q_k = fma(c2, Lm, fma(c1, Lp, f_k)) (2), q_{k-1} - q_k (1), g_k = fma(alpha, q_{k-1} - q_k, f_k) (1).
+OPS_PER_CELL_SWEEP = 9.5
 METRIC = "phase-space cell updates/s (FP32 vs FP64 GPU) + % HBM roofline"
 
 
