@@ -277,26 +277,82 @@ __global__ void gradient_kernel(double* a, const double* phi, Grid3 n, double d0
   }
 }
 
-template <typename T>
+// Cell counters (i0, i1, i2) of a row-major box m0 x m1 x m2, advanced by a
+// fixed stride without integer division. The stride is split once into its
+// own counters, whose i2 part is below m2 and i1 part below m1, so each step
+// carries at most once per axis. Counters past the end of the box are never
+// read.
+struct Idx3 {
+  int i0, i1, i2;
+  static __device__ __forceinline__ Idx3 split(long long e, int m1, int m2)
+  {
+    Idx3 c;
+    c.i2 = (int)(e % m2);
+    const long long r = e / m2;
+    c.i1 = (int)(r % m1);
+    c.i0 = (int)(r / m1);
+    return c;
+  }
+  __device__ __forceinline__ void step(const Idx3& d, int m1, int m2)
+  {
+    i2 += d.i2;
+    if (i2 >= m2) {
+      i2 -= m2;
+      ++i1;
+    }
+    i1 += d.i1;
+    if (i1 >= m1) {
+      i1 -= m1;
+      ++i0;
+    }
+    i0 += d.i0;
+  }
+};
+
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Pack {
+  T v[V];
+};
+
+// Per spatial cell: sum_j f_j and sum_j f_j |v_j|^2 over its velocity block
+// (Eqs. (29), (30) before the dx^3 dv^3 factor). A lane loads V consecutive
+// cells of one vz-line at a time (16 bytes when nv_z is a multiple of V, else
+// V = 1), four loads in flight, and walks the velocity indices with Idx3.
+template <typename T, int V>
 __global__ __launch_bounds__(RED) void energy_partial_kernel(const T* f, double* part, VelGrid vg)
 {
   __shared__ double sh[RED];
-  const long long nv3 = (long long)vg.nv[0] * vg.nv[1] * vg.nv[2];
-  const T* p = f + (long long)blockIdx.x * nv3;
-  double m = 0.0, k = 0.0;
-  for (long long j = threadIdx.x; j < nv3; j += RED) {
-    const int jz = (int)(j % vg.nv[2]);
-    const int jy = (int)((j / vg.nv[2]) % vg.nv[1]);
-    const int jx = (int)(j / ((long long)vg.nv[2] * vg.nv[1]));
-    const double vx = vg.vmin[0] + (jx + 0.5) * vg.dv[0];
-    const double vy = vg.vmin[1] + (jy + 0.5) * vg.dv[1];
-    const double vz = vg.vmin[2] + (jz + 0.5) * vg.dv[2];
-    const double x = (double)p[j];
-    m += x;
-    k += x * (vx * vx + vy * vy + vz * vz);
+  const int ny = vg.nv[1], nz = vg.nv[2];
+  const long long nv3 = (long long)vg.nv[0] * ny * nz;
+  const long long ngrp = nv3 / V;
+  const Pack<T, V>* p = reinterpret_cast<const Pack<T, V>*>(f + (long long)blockIdx.x * nv3);
+  Idx3 c = Idx3::split((long long)threadIdx.x * V, ny, nz);
+  const Idx3 d = Idx3::split((long long)RED * V, ny, nz);
+  double m[4] = {0.0, 0.0, 0.0, 0.0}, k[4] = {0.0, 0.0, 0.0, 0.0};
+  auto add = [&](const Pack<T, V>& q, int a) {
+    const double vx = vg.vmin[0] + (c.i0 + 0.5) * vg.dv[0];
+    const double vy = vg.vmin[1] + (c.i1 + 0.5) * vg.dv[1];
+    const double wxy = vx * vx + vy * vy;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const double vz = vg.vmin[2] + (c.i2 + e + 0.5) * vg.dv[2];
+      const double x = (double)q.v[e];
+      m[a] += x;
+      k[a] += x * (wxy + vz * vz);
+    }
+    c.step(d, ny, nz);
+  };
+  long long g = threadIdx.x;
+  for (; g + 3 * RED < ngrp; g += 4 * RED) {
+    const Pack<T, V> q0 = p[g], q1 = p[g + RED], q2 = p[g + 2 * RED], q3 = p[g + 3 * RED];
+    add(q0, 0);
+    add(q1, 1);
+    add(q2, 2);
+    add(q3, 3);
   }
-  const double ms = block_sum(m, sh);
-  const double ks = block_sum(k, sh);
+  for (; g < ngrp; g += RED) add(p[g], 0);
+  const double ms = block_sum((m[0] + m[1]) + (m[2] + m[3]), sh);
+  const double ks = block_sum((k[0] + k[1]) + (k[2] + k[3]), sh);
   if (threadIdx.x == 0) {
     part[2 * (long long)blockIdx.x] = ms;
     part[2 * (long long)blockIdx.x + 1] = ks;
@@ -309,14 +365,14 @@ __global__ __launch_bounds__(RED) void energy_final_kernel(double* out, const do
   __shared__ double sh[RED];
   const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
   const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  Idx3 c = Idx3::split(threadIdx.x, n.m[1], n.m[2]);
+  const Idx3 d = Idx3::split(RED, n.m[1], n.m[2]);
   double m = 0.0, k = 0.0, u = 0.0;
   for (long long s = threadIdx.x; s < np; s += RED) {
     m += part[2 * s];
     k += part[2 * s + 1];
-    const long long i2 = s % n.m[2];
-    const long long i1 = (s / n.m[2]) % n.m[1];
-    const long long i0 = s / ((long long)n.m[2] * n.m[1]);
-    u += rho[s] * phi[((i0 + 1) * e1 + (i1 + 1)) * e2 + (i2 + 1)];
+    u += rho[s] * phi[((c.i0 + 1) * e1 + (c.i1 + 1)) * e2 + (c.i2 + 1)];
+    c.step(d, n.m[1], n.m[2]);
   }
   const double ms = block_sum(m, sh);
   const double ks = block_sum(k, sh);
@@ -472,12 +528,12 @@ __global__ __launch_bounds__(RED) void potential_energy_kernel(double* out, cons
   __shared__ double sh[RED];
   const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
   const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
+  Idx3 c = Idx3::split(threadIdx.x, n.m[1], n.m[2]);
+  const Idx3 d = Idx3::split(RED, n.m[1], n.m[2]);
   double u = 0.0;
   for (long long s = threadIdx.x; s < np; s += RED) {
-    const long long i2 = s % n.m[2];
-    const long long i1 = (s / n.m[2]) % n.m[1];
-    const long long i0 = s / ((long long)n.m[2] * n.m[1]);
-    u += rho[s] * phi[((i0 + 1) * e1 + (i1 + 1)) * e2 + (i2 + 1)];
+    u += rho[s] * phi[((c.i0 + 1) * e1 + (c.i1 + 1)) * e2 + (c.i2 + 1)];
+    c.step(d, n.m[1], n.m[2]);
   }
   const double us = block_sum(u, sh);
   if (threadIdx.x == 0) out[0] = 0.5 * us * dx3;
@@ -673,11 +729,24 @@ hipError_t launch_gradient(double* accel, const double* phi_ext, Grid3 n, double
 
 hipError_t launch_energy_partials(const void* f, int dtype, double* part, long long np, VelGrid vg, hipStream_t s)
 {
-  if (dtype == 0)
-    hipLaunchKernelGGL(energy_partial_kernel<float>, dim3((unsigned)np), dim3(RED), 0, s, (const float*)f, part, vg);
-  else
-    hipLaunchKernelGGL(energy_partial_kernel<double>, dim3((unsigned)np), dim3(RED), 0, s, (const double*)f, part,
-                       vg);
+  // 16-byte groups need whole groups per vz-line and a 16-byte aligned base
+  // (every block then starts aligned, its length being a multiple of V).
+  const bool a16 = (reinterpret_cast<uintptr_t>(f) % 16) == 0;
+  if (dtype == 0) {
+    if (a16 && vg.nv[2] % 4 == 0)
+      hipLaunchKernelGGL((energy_partial_kernel<float, 4>), dim3((unsigned)np), dim3(RED), 0, s,
+                         static_cast<const float*>(f), part, vg);
+    else
+      hipLaunchKernelGGL((energy_partial_kernel<float, 1>), dim3((unsigned)np), dim3(RED), 0, s,
+                         static_cast<const float*>(f), part, vg);
+  } else {
+    if (a16 && vg.nv[2] % 2 == 0)
+      hipLaunchKernelGGL((energy_partial_kernel<double, 2>), dim3((unsigned)np), dim3(RED), 0, s,
+                         static_cast<const double*>(f), part, vg);
+    else
+      hipLaunchKernelGGL((energy_partial_kernel<double, 1>), dim3((unsigned)np), dim3(RED), 0, s,
+                         static_cast<const double*>(f), part, vg);
+  }
   return hipGetLastError();
 }
 
