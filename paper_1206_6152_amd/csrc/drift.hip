@@ -172,6 +172,130 @@ __global__ __launch_bounds__((DriftShape<T, NY, NZ, W>::THREADS)) void drift_yz_
   }
 }
 
+// ---- one-pass drift, two lines per lane -------------------------------------
+// The same two sweeps on tiles of W velocity cells, with lane (i, p) of the
+// NP x W/2 lanes holding the lines of the adjacent cells 2p and 2p + 1 of the
+// tile. The z lines (y = i) come in as 8- or 16-byte pairs, so that a row of
+// W/2 lanes reads one whole W-cell run, and are swept in registers; they reach
+// the y sweep through LDS in two rounds (cells 2p, then cells 2p + 1) of W/2
+// columns, half the LDS that one line per lane needs. In the second phase lane
+// (i, p) takes the y lines (z = i) of the same two cells. With nv_z even the
+// two cells of a pair share vy, hence the y sweep's coefficients, shift and
+// orientation, so the y lines go back to HBM as pairs too. Byte offsets are
+// 64-bit: a tile may span more than 4 GiB (64 x 64 planes of 1 MiB blocks).
+template <typename T, int NP, int W>
+struct DrPairShape {
+  static constexpr int H = W / 2;                                  // LDS columns per round
+  static constexpr int SY0 = NP * H;
+  static constexpr int SY = SY0 + ((((H - SY0) % 64) + 64) % 64);   // = H (mod 64)
+  static constexpr int ELEMS = NP * SY;
+  static constexpr int BYTES = ELEMS * (int)sizeof(T);
+  static constexpr int THREADS = NP * H;
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && THREADS % 64 == 0 && W % 2 == 0;
+};
+
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
+template <>
+struct Pair2<double> {
+  using type = double2;
+};
+
+template <typename T, int NP, int W, int TILES>
+__global__ __launch_bounds__((DrPairShape<T, NP, W>::THREADS)) void drift_yz_pairs(DriftArgs a)
+{
+  using S = DrPairShape<T, NP, W>;
+  using P2 = typename Pair2<T>::type;
+  constexpr int H = S::H;
+  __shared__ T L[S::ELEMS];
+  const int tid = threadIdx.x;
+  const int i0 = tid / H, p = tid - i0 * H;
+  const long long nchunk = a.nv3 / W;
+  const long long upx = (nchunk + TILES - 1) / TILES;   // workgroups per x index
+  const long long ix = blockIdx.x / upx, cg = blockIdx.x - ix * upx;
+  const bool periodic = a.periodic != 0;
+  const LineTab<T>* zt = static_cast<const LineTab<T>*>(a.tab);
+  const LineTab<T>* yt = zt + a.nv3;
+  const long long RB = a.nv3 * (long long)sizeof(T);   // bytes from one z to the next
+  char* slab = static_cast<char*>(a.f) + ix * NP * NP * RB;
+#pragma unroll 1
+  for (int k = 0; k < TILES; k++) {
+    const long long jc = cg * TILES + k;
+    if (jc >= nchunk) break;                            // uniform over the workgroup
+    char* tile = slab + (jc * W + 2 * p) * (long long)sizeof(T);
+    T v0[NP], v1[NP];
+    {
+      const char* src = tile + (long long)i0 * NP * RB;
+#pragma unroll
+      for (int r = 0; r < NP; r++) {
+        const P2 x = *reinterpret_cast<const P2*>(src + r * RB);
+        v0[r] = x.x;
+        v1[r] = x.y;
+      }
+    }
+    const long long j = jc * W + 2 * p;
+    const LineTab<T> cz0 = zt[j], cz1 = zt[j + 1], cy0 = yt[j], cy1 = yt[j + 1];
+    // z lines, mirrored where vz < 0, take the forward update
+    auto zsweep = [&](T(&v)[NP], const LineTab<T>& c) {
+      const bool rz = (c.meta >> 16) & 1;
+#pragma unroll
+      for (int i = 0; i < NP / 2; i++) {
+        const T x0 = v[i], x1 = v[NP - 1 - i];
+        v[i] = rz ? x1 : x0;
+        v[NP - 1 - i] = rz ? x0 : x1;
+      }
+      pfc_core<T, NP>(v, c.alpha, c.c1, c.c2, periodic);
+    };
+    zsweep(v0, cz0);
+    zsweep(v1, cz1);
+    // one round: the z lines of one cell per lane are parked in LDS (at their
+    // y place in the y sweep's orientation), and each lane takes back the y
+    // line of storage z = i of the same cell, found at LDS z place i, or
+    // NP-1-i where vz < 0
+    auto round = [&](T(&v)[NP], const LineTab<T>& cz, const LineTab<T>& cy) {
+      const bool ry = (cz.meta >> 17) & 1;
+      const int base = (ry ? NP - 1 - i0 : i0) * S::SY + p;
+      store_shifted<T, NP>(v, tab_shift(cz.meta), periodic, [&](int r, T x) { L[base + r * H] = x; });
+      __syncthreads();
+      const bool rz = (cy.meta >> 16) & 1;
+      const int yb = (rz ? NP - 1 - i0 : i0) * H + p;
+#pragma unroll
+      for (int r = 0; r < NP; r++) v[r] = L[yb + r * S::SY];
+      pfc_core<T, NP>(v, cy.alpha, cy.c1, cy.c2, periodic);
+      __syncthreads();                                  // LDS is reused by the next round
+    };
+    round(v0, cz0, cy0);
+    round(v1, cz1, cy1);
+    // row r of the y lines goes to storage y = r, or NP-1-r where vy < 0
+    const bool ry = (cy0.meta >> 17) & 1;
+    const long long ystep = NP * RB;
+    char* dst = tile + (long long)i0 * RB + (ry ? (NP - 1) * ystep : 0LL);
+    const long long yst = ry ? -ystep : ystep;
+    store_shifted2<T, NP>(v0, v1, tab_shift(cy0.meta), periodic,
+                          [&](int r, T x0, T x1) { *reinterpret_cast<P2*>(dst + r * yst) = P2{x0, x1}; });
+  }
+}
+
+template <typename T, int NP, int W, int TILES>
+hipError_t launch_drift_yz_pairs(const DriftArgs& a, hipStream_t s)
+{
+  using S = DrPairShape<T, NP, W>;
+  static_assert(S::fits, "tile does not fit the LDS");
+  const long long nchunk = a.nv3 / W;
+  if (a.nx <= 0 || nchunk <= 0) return hipSuccess;
+  if (a.nv3 % W != 0 || a.nvz % 2 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((drift_table_kernel<T, NP, NP>), dim3((unsigned)((a.nv3 + 255) / 256)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long wgs = a.nx * ((nchunk + TILES - 1) / TILES);
+  hipLaunchKernelGGL((drift_yz_pairs<T, NP, W, TILES>), dim3((unsigned)wgs), dim3(S::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int NP, int W, int TILES>
 hipError_t launch_drift_yz_sq(const DriftArgs& a0, hipStream_t s)
 {
@@ -193,42 +317,43 @@ hipError_t launch_drift_yz_sq(const DriftArgs& a0, hipStream_t s)
 
 }  // namespace
 
-// (y, z) planes of 16, 24 or 32 cells with whole-cache-line velocity chunks
-// Velocity cells per chunk (W), tiles per workgroup, and chunks per cache
-// line (G) of the one-pass T_z T_y: whole-line chunks up to 32-cell planes;
-// 48-cell planes take half-line chunks (FP32 16 cells, FP64 8), whose
-// workgroups are grouped per line (above). 64-cell planes would take quarter
-// lines (32 bytes); measured on the 16 x 64 x 64 slab, that pass took 2.7
-// times a plain sweep, so those planes keep two plain sweeps.
+// Velocity cells per chunk (W), tiles per workgroup, chunks per cache line (G)
+// and kernel of the one-pass T_z T_y. One line per lane (drift_yz_block):
+// whole-line chunks for 16- to 32-cell planes, half-line chunks for 48-cell
+// planes, whose workgroups are grouped per line (above). Two lines per lane
+// (drift_yz_pairs, nv_z even): 64-cell FP32 planes in 16-cell chunks.
 struct DriftPlan {
-  int w, tiles, g;
+  int w, tiles, g, pairs;
 };
 
-static DriftPlan drift_plan(int dtype, int ny, int nz, long long nv3)
+static DriftPlan drift_plan(int dtype, int ny, int nz, long long nv3, long long nvz)
 {
-  DriftPlan p{0, 0, 1};
-  if (ny != nz) return p;
+  DriftPlan p{0, 0, 1, 0};
+  if (ny != nz || nv3 <= 0) return p;
   const int es = dtype == 0 ? 4 : 8;
   if (dtype == 0) {
     switch (ny) {
-      case 16: p = {64, 4, 1}; break;
-      case 24: case 32: p = {32, 4, 1}; break;
-      case 48: p = {16, 4, 2}; break;
-      default: return DriftPlan{0, 0, 1};
+      case 16: p = {64, 4, 1, 0}; break;
+      case 24: p = {32, 4, 1, 0}; break;
+      case 32: p = {32, 4, 1, 1}; break;
+      case 48: p = {32, 4, 1, 1}; break;
+      case 64: p = {16, 4, 1, 1}; break;
+      default: return DriftPlan{0, 0, 1, 0};
     }
   } else {
     switch (ny) {
-      case 16: p = {32, 2, 1}; break;
-      case 24: p = {16, 2, 1}; break;
-      case 32: p = {16, 4, 1}; break;
-      case 48: p = {8, 2, 2}; break;
-      default: return DriftPlan{0, 0, 1};
+      case 16: p = {32, 2, 1, 0}; break;
+      case 24: p = {16, 2, 1, 0}; break;
+      case 32: p = {16, 4, 1, 1}; break;
+      case 48: p = {8, 2, 2, 0}; break;
+      default: return DriftPlan{0, 0, 1, 0};
     }
   }
-  if (nv3 % p.w != 0) return DriftPlan{0, 0, 1};
-  if (p.g > 1 && (nv3 / p.w) % (p.tiles * p.g) != 0) return DriftPlan{0, 0, 1};
+  if (nv3 % p.w != 0) return DriftPlan{0, 0, 1, 0};
+  if (p.pairs) return nvz % 2 == 0 ? p : DriftPlan{0, 0, 1, 0};
+  if (p.g > 1 && (nv3 / p.w) % (p.tiles * p.g) != 0) return DriftPlan{0, 0, 1, 0};
   // 32-bit byte offsets within a tile: the largest is under the tile's span
-  if (((long long)ny * nz * nv3 - nv3 + p.w) * es >= (1LL << 32)) return DriftPlan{0, 0, 1};
+  if (((long long)ny * nz * nv3 - nv3 + p.w) * es >= (1LL << 32)) return DriftPlan{0, 0, 1, 0};
   return p;
 }
 
@@ -237,27 +362,29 @@ size_t drift_table_bytes(int dtype, long long nv3)
   return (size_t)(2 * nv3) * (dtype == 0 ? sizeof(LineTab<float>) : sizeof(LineTab<double>));
 }
 
-bool drift_yz_supported(int dtype, int ny, int nz, long long nv3) { return drift_plan(dtype, ny, nz, nv3).w != 0; }
+bool drift_yz_supported(int dtype, int ny, int nz, long long nv3, long long nvz)
+{
+  return drift_plan(dtype, ny, nz, nv3, nvz).w != 0;
+}
 
-// Tiles per workgroup: four, except two for the FP64 16- and 24-planes, whose
-// workgroups are small enough that several share a CU anyway, and for the
-// FP64 48-planes.
 hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
 {
-  if (!a.tab || drift_plan(dtype, a.ny, a.nz, a.nv3).w == 0) return hipErrorInvalidValue;
+  const DriftPlan p = drift_plan(dtype, a.ny, a.nz, a.nv3, a.nvz);
+  if (!a.tab || p.w == 0) return hipErrorInvalidValue;
   if (dtype == 0) {
     switch (a.ny) {
       case 16: return launch_drift_yz_sq<float, 16, 64, 4>(a, s);
       case 24: return launch_drift_yz_sq<float, 24, 32, 4>(a, s);
-      case 32: return launch_drift_yz_sq<float, 32, 32, 4>(a, s);
-      case 48: return launch_drift_yz_sq<float, 48, 16, 4>(a, s);
+      case 32: return launch_drift_yz_pairs<float, 32, 32, 4>(a, s);
+      case 48: return launch_drift_yz_pairs<float, 48, 32, 4>(a, s);
+      case 64: return launch_drift_yz_pairs<float, 64, 16, 4>(a, s);
       default: break;
     }
   } else {
     switch (a.ny) {
       case 16: return launch_drift_yz_sq<double, 16, 32, 2>(a, s);
       case 24: return launch_drift_yz_sq<double, 24, 16, 2>(a, s);
-      case 32: return launch_drift_yz_sq<double, 32, 16, 4>(a, s);
+      case 32: return launch_drift_yz_pairs<double, 32, 16, 4>(a, s);
       case 48: return launch_drift_yz_sq<double, 48, 8, 2>(a, s);
       default: break;
     }

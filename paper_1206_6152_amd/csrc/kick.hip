@@ -214,7 +214,10 @@ template <typename T, int NV, int PASS, int CH_ = NV / 2>
 struct PairShape {
   static constexpr int CH = CH_;                         // planes across the third axis
   static constexpr int NCH = NV / CH;                    // slices per velocity block
-  static constexpr int PAD = 64 / (int)sizeof(T);
+  // PASS 0 vx rows of SA = NV CH + PAD elements, SA = CH (mod the 64 banks
+  // of 4 bytes), so that the T_vy lanes (vx, c) of a wave take distinct banks
+  static constexpr int WD = (int)sizeof(T) / 4;           // banks per element
+  static constexpr int PAD = ((CH_ - NV * CH_) * WD % 64 + 64) % 64 / WD;
   static constexpr int SR = NV + 1;                       // padded vz row (PASS 1, 2)
   // PASS 0: [vx][vy][c], vx stride SA; PASS 1: [vx][c][vz]; PASS 2: [c][vy][vz]
   static constexpr int SA = NV * CH + PAD;

@@ -156,5 +156,35 @@ __device__ __forceinline__ void store_shifted(const T (&v)[N], int shift, bool p
   }
 }
 
+// store_shifted for two lines that take the same shift: st(i, x0, x1) sets
+// cell i of both, so that the caller can write the pair with one access.
+template <typename T, int N, typename ST>
+__device__ __forceinline__ void store_shifted2(const T (&v0)[N], const T (&v1)[N], int shift, bool periodic, ST st)
+{
+  if (shift == 0) {
+#pragma unroll
+    for (int r = 0; r < N; r++) st(r, v0[r], v1[r]);
+    return;
+  }
+  asm volatile("" : "+v"(shift));
+#pragma unroll
+  for (int r = 0; r < N; r++) {
+    int d = r + shift;
+    if (periodic) {
+      d %= N;
+      if (d < 0) d += N;
+      st(d, v0[r], v1[r]);
+    } else if (d >= 0 && d < N) {
+      st(d, v0[r], v1[r]);
+    }
+  }
+  if (!periodic) {
+    for (int i = 0; i < N; i++) {
+      const int src = i - shift;
+      if (src < 0 || src >= N) st(i, T(0), T(0));
+    }
+  }
+}
+
 }  // namespace
 }  // namespace vp

@@ -566,7 +566,7 @@ int drift(vp_ctx* c, double tau, bool x_sums = false)
 {
   int r;
   const auto& k = c->cfg;
-  if (vp::drift_yz_supported(k.dtype, k.n[1], k.n[2], c->nv3)) {
+  if (vp::drift_yz_supported(k.dtype, k.n[1], k.n[2], c->nv3, k.nv[2])) {
     vp::DriftArgs a{};
     a.f = c->f;
     a.nx = k.n[0];
@@ -726,7 +726,7 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
       return r;
     }
   }
-  if (vp::drift_yz_supported(cfg->dtype, cfg->n[1], cfg->n[2], c->nv3) &&
+  if (vp::drift_yz_supported(cfg->dtype, cfg->n[1], cfg->n[2], c->nv3, cfg->nv[2]) &&
       (r = dalloc(&c->dtab, vp::drift_table_bytes(cfg->dtype, c->nv3), "drift coefficients"))) {
     release(c);
     return r;

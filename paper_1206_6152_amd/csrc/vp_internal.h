@@ -107,7 +107,7 @@ struct DriftArgs {
   int xcd_group;  // set by launch_drift_yz: chunks that share cache lines on one XCD
 };
 size_t drift_table_bytes(int dtype, long long nv3);
-bool drift_yz_supported(int dtype, int ny, int nz, long long nv3);
+bool drift_yz_supported(int dtype, int ny, int nz, long long nv3, long long nvz);
 hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s);
 
 // ---- gravity and reductions (FP64) ----------------------------------------

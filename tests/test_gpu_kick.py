@@ -170,12 +170,12 @@ def test_run_equals_repeated_steps(shape, dtype):
                                                 (VP_F64, 48, 2, (4, 4, 8)), (VP_F64, 64, 2, (2, 4, 16))])
 def test_one_pass_drift_many_tiles_per_workgroup(dtype, plane, nx, nv):
     # a workgroup walks several (x, velocity chunk) tiles (four, or two for
-    # FP64 planes of 16 and 24) and loads the next one while it sweeps the
-    # current one; the tile counts here include ragged ends (9 and 3 tiles in
-    # FP32; 9, 3 and 9 in FP64). The 48-planes take chunks narrower than a
-    # cache line, and these cases have a multiple of 8 workgroup units, so the
-    # workgroups that share lines are grouped per XCD (64-planes keep two
-    # plain sweeps; their cases check that route).
+    # FP64 planes of 16, 24 and 48); the tile counts here include ragged ends
+    # (9 and 3 tiles in FP32; 9, 3 and 9 in FP64). The FP64 48-planes take
+    # chunks narrower than a cache line, and their case has a multiple of 8
+    # workgroup units, so the workgroups that share lines are grouped per XCD.
+    # FP32 planes of 32, 48 and 64 and FP64 planes of 32 hold two lines per
+    # lane; FP64 64-planes keep two plain sweeps.
     print("case", dtype, plane, nx, nv, flush=True)
     w = small_workload(VP_BC_PERIODIC, n=(nx, plane, plane), nv=nv)
     w = w.__class__(name="d", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
@@ -184,6 +184,40 @@ def test_one_pass_drift_many_tiles_per_workgroup(dtype, plane, nx, nv):
     f0 = (structured_f(w.shape, seed=plane) + 1e-3 * rng.uniform(0, 1, w.shape)).astype(NP[dtype]).astype(np.float64)
     a = np.zeros((3,) + w.n)
     tau = 1.3 * 0.25 / 2.0
+    sim, f = _sim(w, f0, dtype, a)
+    sim.drift(tau)
+    out = f.cpu().numpy()
+    sim.close()
+    sim, f = _sim(w, f0, dtype, a)
+    for ax in (2, 1, 0):
+        sim.sweep(ax, tau)
+    split = f.cpu().numpy()
+    sim.close()
+    assert np.array_equal(out, split)
+    g = oracle_grid(w)
+    ref = f0
+    for ax in (2, 1, 0):
+        ref = oracle.sweep(g, ref, ax, tau)
+    assert rel_l1(out, ref) <= (1e-14 if dtype == VP_F64 else 2e-6)
+
+
+@pytest.mark.parametrize("dtype,plane,nv", [(VP_F32, 32, (2, 8, 6)), (VP_F32, 48, (2, 8, 6)), (VP_F32, 64, (2, 4, 6)),
+                                            (VP_F64, 32, (2, 4, 6)), (VP_F32, 32, (2, 16, 3)),
+                                            (VP_F32, 64, (1, 16, 3))])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+def test_one_pass_drift_pairs_of_cells(dtype, plane, nv, bc):
+    # the two-lines-per-lane drift holds velocity cells 2p and 2p + 1 in one
+    # lane: with nv_z = 6 the pair (2, 3) straddles vz = 0, so its two z lines
+    # run in opposite orientations while sharing the y sweep. With nv_z odd a
+    # pair would straddle a vz row, so the drift takes the single sweeps.
+    print("case", dtype, plane, nv, bc, flush=True)
+    w = small_workload(bc, n=(3, plane, plane), nv=nv)
+    w = w.__class__(name="d", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
+                    vmax=(1.5, 2.0, 1.5), G=1.0, bc=bc)
+    rng = np.random.default_rng(plane + nv[2])
+    f0 = (structured_f(w.shape, seed=plane) + 1e-3 * rng.uniform(0, 1, w.shape)).astype(NP[dtype]).astype(np.float64)
+    a = np.zeros((3,) + w.n)
+    tau = 1.7 * 0.25 / 2.0
     sim, f = _sim(w, f0, dtype, a)
     sim.drift(tau)
     out = f.cpu().numpy()
