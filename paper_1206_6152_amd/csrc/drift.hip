@@ -205,7 +205,7 @@ struct Pair2<double> {
   using type = double2;
 };
 
-template <typename T, int NP, int W, int TILES>
+template <typename T, int NP, int W, int TILES, int G>
 __global__ __launch_bounds__((DrPairShape<T, NP, W>::THREADS)) void drift_yz_pairs(DriftArgs a)
 {
   using S = DrPairShape<T, NP, W>;
@@ -215,8 +215,20 @@ __global__ __launch_bounds__((DrPairShape<T, NP, W>::THREADS)) void drift_yz_pai
   const int tid = threadIdx.x;
   const int i0 = tid / H, p = tid - i0 * H;
   const long long nchunk = a.nv3 / W;
-  const long long upx = (nchunk + TILES - 1) / TILES;   // workgroups per x index
-  const long long ix = blockIdx.x / upx, cg = blockIdx.x - ix * upx;
+  const long long upx = (nchunk / G + TILES - 1) / TILES;   // units per x index
+  // the G workgroups of a unit take the G chunks of each cache line (grouped
+  // on one XCD as in drift_yz_block)
+  long long unit;
+  int q;
+  if (G > 1 && a.xcd_group) {
+    const long long b = blockIdx.x, x = b & 7, k = b >> 3;
+    q = (int)(k % G);
+    unit = 8 * (k / G) + x;
+  } else {
+    q = (int)(blockIdx.x % G);
+    unit = blockIdx.x / G;
+  }
+  const long long ix = unit / upx, cg = unit - ix * upx;
   const bool periodic = a.periodic != 0;
   const LineTab<T>* zt = static_cast<const LineTab<T>*>(a.tab);
   const LineTab<T>* yt = zt + a.nv3;
@@ -224,8 +236,8 @@ __global__ __launch_bounds__((DrPairShape<T, NP, W>::THREADS)) void drift_yz_pai
   char* slab = static_cast<char*>(a.f) + ix * NP * NP * RB;
 #pragma unroll 1
   for (int k = 0; k < TILES; k++) {
-    const long long jc = cg * TILES + k;
-    if (jc >= nchunk) break;                            // uniform over the workgroup
+    const long long jc = (cg * TILES + k) * G + q;
+    if (jc >= nchunk) break;                            // uniform over the workgroup (ragged ends: G = 1)
     char* tile = slab + (jc * W + 2 * p) * (long long)sizeof(T);
     T v0[NP], v1[NP];
     {
@@ -280,19 +292,22 @@ __global__ __launch_bounds__((DrPairShape<T, NP, W>::THREADS)) void drift_yz_pai
   }
 }
 
-template <typename T, int NP, int W, int TILES>
-hipError_t launch_drift_yz_pairs(const DriftArgs& a, hipStream_t s)
+template <typename T, int NP, int W, int TILES, int G>
+hipError_t launch_drift_yz_pairs(const DriftArgs& a0, hipStream_t s)
 {
   using S = DrPairShape<T, NP, W>;
   static_assert(S::fits, "tile does not fit the LDS");
-  const long long nchunk = a.nv3 / W;
-  if (a.nx <= 0 || nchunk <= 0) return hipSuccess;
-  if (a.nv3 % W != 0 || a.nvz % 2 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((drift_table_kernel<T, NP, NP>), dim3((unsigned)((a.nv3 + 255) / 256)), dim3(256), 0, s, a);
+  const long long nchunk = a0.nv3 / W;
+  if (a0.nx <= 0 || nchunk <= 0) return hipSuccess;
+  if (a0.nv3 % W != 0 || a0.nvz % 2 != 0) return hipErrorInvalidValue;
+  if (G > 1 && nchunk % (TILES * G) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((drift_table_kernel<T, NP, NP>), dim3((unsigned)((a0.nv3 + 255) / 256)), dim3(256), 0, s, a0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long long wgs = a.nx * ((nchunk + TILES - 1) / TILES);
-  hipLaunchKernelGGL((drift_yz_pairs<T, NP, W, TILES>), dim3((unsigned)wgs), dim3(S::THREADS), 0, s, a);
+  const long long units = a0.nx * ((nchunk / G + TILES - 1) / TILES);
+  DriftArgs a = a0;
+  a.xcd_group = (G > 1 && units % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((drift_yz_pairs<T, NP, W, TILES, G>), dim3((unsigned)(units * G)), dim3(S::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -337,7 +352,7 @@ static DriftPlan drift_plan(int dtype, int ny, int nz, long long nv3, long long 
       case 24: p = {32, 4, 1, 0}; break;
       case 32: p = {32, 4, 1, 1}; break;
       case 48: p = {32, 4, 1, 1}; break;
-      case 64: p = {16, 4, 1, 1}; break;
+      case 64: p = {16, 4, 2, 1}; break;
       default: return DriftPlan{0, 0, 1, 0};
     }
   } else {
@@ -350,8 +365,8 @@ static DriftPlan drift_plan(int dtype, int ny, int nz, long long nv3, long long 
     }
   }
   if (nv3 % p.w != 0) return DriftPlan{0, 0, 1, 0};
-  if (p.pairs) return nvz % 2 == 0 ? p : DriftPlan{0, 0, 1, 0};
   if (p.g > 1 && (nv3 / p.w) % (p.tiles * p.g) != 0) return DriftPlan{0, 0, 1, 0};
+  if (p.pairs) return nvz % 2 == 0 ? p : DriftPlan{0, 0, 1, 0};
   // 32-bit byte offsets within a tile: the largest is under the tile's span
   if (((long long)ny * nz * nv3 - nv3 + p.w) * es >= (1LL << 32)) return DriftPlan{0, 0, 1, 0};
   return p;
@@ -375,16 +390,16 @@ hipError_t launch_drift_yz(const DriftArgs& a, int dtype, hipStream_t s)
     switch (a.ny) {
       case 16: return launch_drift_yz_sq<float, 16, 64, 4>(a, s);
       case 24: return launch_drift_yz_sq<float, 24, 32, 4>(a, s);
-      case 32: return launch_drift_yz_pairs<float, 32, 32, 4>(a, s);
-      case 48: return launch_drift_yz_pairs<float, 48, 32, 4>(a, s);
-      case 64: return launch_drift_yz_pairs<float, 64, 16, 4>(a, s);
+      case 32: return launch_drift_yz_pairs<float, 32, 32, 4, 1>(a, s);
+      case 48: return launch_drift_yz_pairs<float, 48, 32, 4, 1>(a, s);
+      case 64: return launch_drift_yz_pairs<float, 64, 16, 4, 2>(a, s);
       default: break;
     }
   } else {
     switch (a.ny) {
       case 16: return launch_drift_yz_sq<double, 16, 32, 2>(a, s);
       case 24: return launch_drift_yz_sq<double, 24, 16, 2>(a, s);
-      case 32: return launch_drift_yz_pairs<double, 32, 16, 4>(a, s);
+      case 32: return launch_drift_yz_pairs<double, 32, 16, 4, 1>(a, s);
       case 48: return launch_drift_yz_sq<double, 48, 8, 2>(a, s);
       default: break;
     }

@@ -201,15 +201,18 @@ def test_one_pass_drift_many_tiles_per_workgroup(dtype, plane, nx, nv):
     assert rel_l1(out, ref) <= (1e-14 if dtype == VP_F64 else 2e-6)
 
 
-@pytest.mark.parametrize("dtype,plane,nv", [(VP_F32, 32, (2, 8, 6)), (VP_F32, 48, (2, 8, 6)), (VP_F32, 64, (2, 4, 6)),
-                                            (VP_F64, 32, (2, 4, 6)), (VP_F32, 32, (2, 16, 3)),
-                                            (VP_F32, 64, (1, 16, 3))])
+@pytest.mark.parametrize("dtype,plane,nv", [(VP_F32, 32, (2, 8, 6)), (VP_F32, 48, (2, 8, 6)), (VP_F32, 64, (1, 64, 6)),
+                                            (VP_F32, 64, (2, 4, 6)), (VP_F64, 32, (2, 4, 6)),
+                                            (VP_F32, 32, (2, 16, 3)), (VP_F32, 64, (1, 16, 3))])
 @pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
 def test_one_pass_drift_pairs_of_cells(dtype, plane, nv, bc):
     # the two-lines-per-lane drift holds velocity cells 2p and 2p + 1 in one
     # lane: with nv_z = 6 the pair (2, 3) straddles vz = 0, so its two z lines
-    # run in opposite orientations while sharing the y sweep. With nv_z odd a
-    # pair would straddle a vz row, so the drift takes the single sweeps.
+    # run in opposite orientations while sharing the y sweep. The 64-planes
+    # take half-line chunks whose two workgroups per line are grouped per XCD
+    # (24 chunks); with 3 chunks they cannot pair up and the drift takes the
+    # single sweeps, as it does with nv_z odd, where a pair would straddle a
+    # vz row.
     print("case", dtype, plane, nv, bc, flush=True)
     w = small_workload(bc, n=(3, plane, plane), nv=nv)
     w = w.__class__(name="d", n=w.n, nv=w.nv, L=tuple(0.25 * x for x in w.n), vmin=(-1.0, -2.0, -1.5),
