@@ -196,7 +196,8 @@ int vp_stream_copy(const void* src_dev, void* dst_dev, int64_t nbytes, void* hip
  * nothing of the cell's own offset; this library reads the kernel as
  * -G dx dy dz / |r| away from zero and -G times this integral at zero (the
  * potential of a uniform cell at its centre). Pure host arithmetic, no device
- * and no context; returns NaN unless all three widths are finite and > 0. */
+ * and no context; returns NaN, with a message for vp_last_error, unless all
+ * three widths are finite and > 0. */
 double vp_cell_self_integral(double dx, double dy, double dz);
 
 /* ---- reverse mode (gradients; an extension beyond the paper) -------------

@@ -359,20 +359,53 @@ __global__ __launch_bounds__(RED) void energy_partial_kernel(const T* f, double*
   }
 }
 
-__global__ __launch_bounds__(RED) void energy_final_kernel(double* out, const double* part, const double* rho,
-                                                           const double* phi, Grid3 n, double dx3, double dv3)
+// Whole-grid reductions in two stages: REDUCE_BLOCKS workgroups (fewer for a
+// small grid) each reduce a fixed grid-stride share of the spatial cells into
+// out[RED_PART + ...], then one workgroup combines the partials in order. The
+// grid size depends only on the cell count, so the sums are deterministic.
+__host__ __device__ constexpr int reduce_blocks(long long np)
+{
+  return (int)(np / RED + 1 < REDUCE_BLOCKS ? np / RED + 1 : REDUCE_BLOCKS);
+}
+
+// stage 1 of vp_energy: per workgroup sums of M, K (from the per-cell
+// partials) and of rho phi over its cells
+__global__ __launch_bounds__(RED) void energy_stage_kernel(double* out, const double* part, const double* rho,
+                                                           const double* phi, Grid3 n)
 {
   __shared__ double sh[RED];
   const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
   const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
-  Idx3 c = Idx3::split(threadIdx.x, n.m[1], n.m[2]);
-  const Idx3 d = Idx3::split(RED, n.m[1], n.m[2]);
+  const long long s0 = (long long)blockIdx.x * RED + threadIdx.x, st = (long long)gridDim.x * RED;
+  Idx3 c = Idx3::split(s0, n.m[1], n.m[2]);
+  const Idx3 d = Idx3::split(st, n.m[1], n.m[2]);
   double m = 0.0, k = 0.0, u = 0.0;
-  for (long long s = threadIdx.x; s < np; s += RED) {
+  for (long long s = s0; s < np; s += st) {
     m += part[2 * s];
     k += part[2 * s + 1];
     u += rho[s] * phi[((c.i0 + 1) * e1 + (c.i1 + 1)) * e2 + (c.i2 + 1)];
     c.step(d, n.m[1], n.m[2]);
+  }
+  const double ms = block_sum(m, sh);
+  const double ks = block_sum(k, sh);
+  const double us = block_sum(u, sh);
+  if (threadIdx.x == 0) {
+    double* o = out + RED_PART + 3 * (long long)blockIdx.x;
+    o[0] = ms;
+    o[1] = ks;
+    o[2] = us;
+  }
+}
+
+__global__ __launch_bounds__(RED) void energy_final_kernel(double* out, int nb, double dx3, double dv3)
+{
+  __shared__ double sh[RED];
+  double m = 0.0, k = 0.0, u = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RED) {
+    const double* o = out + RED_PART + 3 * (long long)b;
+    m += o[0];
+    k += o[1];
+    u += o[2];
   }
   const double ms = block_sum(m, sh);
   const double ks = block_sum(k, sh);
@@ -387,16 +420,25 @@ __global__ __launch_bounds__(RED) void energy_final_kernel(double* out, const do
   }
 }
 
-__global__ __launch_bounds__(RED) void accel_max_kernel(double* out, const double* a, long long np, double i0,
-                                                        double i1, double i2)
+__global__ __launch_bounds__(RED) void accel_max_stage_kernel(double* out, const double* a, long long np, double i0,
+                                                              double i1, double i2)
 {
   __shared__ double sh[RED];
   double m = 0.0;
-  for (long long s = threadIdx.x; s < np; s += RED) {
+  for (long long s = (long long)blockIdx.x * RED + threadIdx.x; s < np; s += (long long)gridDim.x * RED) {
     m = fmax(m, fabs(a[s]) * i0);
     m = fmax(m, fabs(a[np + s]) * i1);
     m = fmax(m, fabs(a[2 * np + s]) * i2);
   }
+  const double r = block_max(m, sh);
+  if (threadIdx.x == 0) out[RED_PART + blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(RED) void max_final_kernel(double* out, int nb)
+{
+  __shared__ double sh[RED];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RED) m = fmax(m, out[RED_PART + b]);
   const double r = block_max(m, sh);
   if (threadIdx.x == 0) out[0] = r;
 }
@@ -522,21 +564,31 @@ __global__ void seed_kernel(T* lam, const double* phi, Grid3 n, long long nv3, d
 }
 
 // out[0] = 1/2 sum rho phi dx3 (the potential energy, fixed order)
-__global__ __launch_bounds__(RED) void potential_energy_kernel(double* out, const double* rho, const double* phi,
-                                                               Grid3 n, double dx3)
+__global__ __launch_bounds__(RED) void potential_stage_kernel(double* out, const double* rho, const double* phi,
+                                                              Grid3 n)
 {
   __shared__ double sh[RED];
   const long long np = (long long)n.m[0] * n.m[1] * n.m[2];
   const long long e1 = n.m[1] + 2, e2 = n.m[2] + 2;
-  Idx3 c = Idx3::split(threadIdx.x, n.m[1], n.m[2]);
-  const Idx3 d = Idx3::split(RED, n.m[1], n.m[2]);
+  const long long s0 = (long long)blockIdx.x * RED + threadIdx.x, st = (long long)gridDim.x * RED;
+  Idx3 c = Idx3::split(s0, n.m[1], n.m[2]);
+  const Idx3 d = Idx3::split(st, n.m[1], n.m[2]);
   double u = 0.0;
-  for (long long s = threadIdx.x; s < np; s += RED) {
+  for (long long s = s0; s < np; s += st) {
     u += rho[s] * phi[((c.i0 + 1) * e1 + (c.i1 + 1)) * e2 + (c.i2 + 1)];
     c.step(d, n.m[1], n.m[2]);
   }
   const double us = block_sum(u, sh);
-  if (threadIdx.x == 0) out[0] = 0.5 * us * dx3;
+  if (threadIdx.x == 0) out[RED_PART + blockIdx.x] = us;
+}
+
+__global__ __launch_bounds__(RED) void sum_final_kernel(double* out, int nb, double scale)
+{
+  __shared__ double sh[RED];
+  double u = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RED) u += out[RED_PART + b];
+  const double us = block_sum(u, sh);
+  if (threadIdx.x == 0) out[0] = scale * us;
 }
 
 unsigned grid_for(long long n, int block)
@@ -607,7 +659,9 @@ hipError_t launch_seed(void* lam, int dtype, const double* phi_ext, Grid3 n, lon
 hipError_t launch_potential_energy(double* out, const double* rho, const double* phi_ext, Grid3 n, double dx3,
                                    hipStream_t s)
 {
-  hipLaunchKernelGGL(potential_energy_kernel, dim3(1), dim3(RED), 0, s, out, rho, phi_ext, n, dx3);
+  const int nb = reduce_blocks((long long)n.m[0] * n.m[1] * n.m[2]);
+  hipLaunchKernelGGL(potential_stage_kernel, dim3(nb), dim3(RED), 0, s, out, rho, phi_ext, n);
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(RED), 0, s, out, nb, 0.5 * dx3);
   return hipGetLastError();
 }
 
@@ -753,14 +807,18 @@ hipError_t launch_energy_partials(const void* f, int dtype, double* part, long l
 hipError_t launch_energy_final(double* out, const double* part, const double* rho, const double* phi_ext, Grid3 n,
                                double dx3, double dv3, hipStream_t s)
 {
-  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(RED), 0, s, out, part, rho, phi_ext, n, dx3, dv3);
+  const int nb = reduce_blocks((long long)n.m[0] * n.m[1] * n.m[2]);
+  hipLaunchKernelGGL(energy_stage_kernel, dim3(nb), dim3(RED), 0, s, out, part, rho, phi_ext, n);
+  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(RED), 0, s, out, nb, dx3, dv3);
   return hipGetLastError();
 }
 
 hipError_t launch_accel_max(double* out, const double* accel, long long np, double i0, double i1, double i2,
                             hipStream_t s)
 {
-  hipLaunchKernelGGL(accel_max_kernel, dim3(1), dim3(RED), 0, s, out, accel, np, i0, i1, i2);
+  const int nb = reduce_blocks(np);
+  hipLaunchKernelGGL(accel_max_stage_kernel, dim3(nb), dim3(RED), 0, s, out, accel, np, i0, i1, i2);
+  hipLaunchKernelGGL(max_final_kernel, dim3(1), dim3(RED), 0, s, out, nb);
   return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ struct vp_ctx {
   double2* kspec = nullptr;   // isolated Green's function spectrum
   double2* tw[3] = {nullptr, nullptr, nullptr};
   double* part = nullptr;     // 2 * np
-  double* red = nullptr;      // 8 doubles on the device
+  double* red = nullptr;      // vp::RED_DOUBLES doubles on the device: results, then partials
   double* host = nullptr;     // 8 pinned doubles
   // reverse-mode work fields (allocated on first use)
   double* lphi = nullptr;     // (N+2)^3
@@ -186,7 +186,11 @@ void gauss_legendre(int n, double* x, double* w)
 // integrated with 16-point Gauss-Legendre panels no wider than h_l / 2.
 double vp_cell_self_integral(double dx, double dy, double dz)
 {
-  if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx + dy + dz)) return NAN;
+  g_err.clear();
+  if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx + dy + dz)) {
+    fail(VP_EINVAL, "cell widths must be finite and > 0");
+    return NAN;
+  }
   const int NG = 16;
   double gx[NG], gw[NG];
   gauss_legendre(NG, gx, gw);
@@ -696,7 +700,7 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
       (r = dalloc(&c->accel, sizeof(double) * 3 * c->np, "accel")) ||
       (r = dalloc(&c->work, sizeof(double2) * wn, "transform work")) ||
       (r = dalloc(&c->part, sizeof(double) * 2 * c->np, "partials")) ||
-      (r = dalloc(&c->red, sizeof(double) * 8, "reduction"))) {
+      (r = dalloc(&c->red, sizeof(double) * vp::RED_DOUBLES, "reduction"))) {
     release(c);
     return r;
   }

@@ -174,6 +174,13 @@ struct VelGrid {
 hipError_t launch_energy_partials(const void* f, int dtype, double* part, long long np,
                                   VelGrid vg, hipStream_t s);
 
+// The whole-grid reductions below take a device buffer `out` of
+// RED_PART + 3 REDUCE_BLOCKS doubles: results in out[0..3], per-workgroup
+// partials from out[RED_PART] on.
+constexpr int REDUCE_BLOCKS = 1024;
+constexpr int RED_PART = 8;
+constexpr int RED_DOUBLES = RED_PART + 3 * REDUCE_BLOCKS;
+
 // out[0..3] = K, U, M, E from the partials, rho and phi_ext (deterministic).
 hipError_t launch_energy_final(double* out, const double* part, const double* rho,
                                const double* phi_ext, Grid3 n, double dx3, double dv3,

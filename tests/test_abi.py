@@ -136,3 +136,5 @@ def test_cell_self_integral_rejects_bad_widths():
     _built()
     for d in [(0.0, 1.0, 1.0), (1.0, -1.0, 1.0), (1.0, 1.0, float("nan")), (float("inf"), 1.0, 1.0)]:
         assert np.isnan(_lib.vp_cell_self_integral(*d))
+        assert "widths" in _lib.vp_last_error()
+    assert np.isfinite(_lib.vp_cell_self_integral(1.0, 1.0, 1.0)) and _lib.vp_last_error() == ""
