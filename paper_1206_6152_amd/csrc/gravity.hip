@@ -2,12 +2,13 @@
 // acceleration and FP64 reductions (Sec. 2.2 and Eqs. (18)-(25), (29), (30),
 // (41) of Yoshikawa, Yoshida & Umemura) for gfx950.
 //
-// The transforms are discrete Fourier transforms done axis by axis: one
-// workgroup takes one line, stages it and the twiddle table in LDS, and every
-// lane produces output frequencies. The spatial grids of this method are small
-// (at most a few hundred cells per axis), and the Poisson solve is a small
-// fraction of a step, so a direct per-line transform is used instead of a
-// general FFT library. All of it runs in FP64.
+// The transforms are done axis by axis: one workgroup takes one line, stages
+// it and the twiddle table in LDS and runs a self-sorting mixed-radix FFT
+// (radices 4, 2 and 3, which cover every axis length the library accepts and
+// its doubling for the isolated solve; a direct sum serves any other length).
+// The spatial grids of this method are small (at most a few hundred cells per
+// axis), so a line fits one workgroup and no FFT library is needed. All of it
+// runs in FP64.
 #include "vp_internal.h"
 
 namespace vp {
@@ -174,6 +175,75 @@ __global__ __launch_bounds__(128) void dft_kernel(double2* data, long long inner
     }
     p[(long long)k * inner] = make_double2(sr, si);
   }
+}
+
+// Radices of the mixed-radix transform: fours, then a two, then threes (every
+// axis length this library accepts, and its doubling, factors so).
+struct FftPlan {
+  int n;
+  int r[24];
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One workgroup per line of the axis: a self-sorting (Stockham) mixed-radix
+// FFT of the line in LDS. A stage of radix R with Ns = product of the earlier
+// radices takes, for t < M/R and k = t mod Ns, the R values t + r M/R, turns
+// them by w^(r k M/(Ns R)), transforms them with the R-point DFT and writes
+// output q to (t / Ns) Ns R + k + q Ns. The twiddle table w is the M-th roots
+// of unity, conjugated for the inverse direction; every index into it is
+// below M. Same result as the direct sum up to rounding (O(log M) eps).
+__global__ __launch_bounds__(128) void fft_kernel(double2* data, long long inner, int M, int sign,
+                                                   const double2* tw, FftPlan plan)
+{
+  extern __shared__ double2 lds[];
+  double2* a = lds;
+  double2* b = lds + M;
+  double2* w = lds + 2 * M;
+  const long long line = blockIdx.x;
+  const long long o = line / inner;
+  const long long c = line - o * inner;
+  double2* p = data + o * (long long)M * inner + c;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    a[j] = p[(long long)j * inner];
+    const double2 t = tw[j];
+    w[j] = make_double2(t.x, sign < 0 ? t.y : -t.y);
+  }
+  __syncthreads();
+  int ns = 1;
+  for (int st = 0; st < plan.n; st++) {
+    const int R = plan.r[st], step = M / R, tws = M / (ns * R);
+    for (int t = threadIdx.x; t < step; t += blockDim.x) {
+      const int k = t % ns;
+      double2 v[4];
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+        if (r < R) v[r] = cmul(a[t + r * step], w[r * k * tws]);
+      const int base = (t / ns) * ns * R + k;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if (q >= R) break;
+        double2 y = v[0];
+#pragma unroll
+        for (int r = 1; r < 4; r++)
+          if (r < R) {
+            const double2 z = cmul(v[r], w[((q * r) % R) * step]);
+            y.x += z.x;
+            y.y += z.y;
+          }
+        b[base + q * ns] = y;
+      }
+    }
+    __syncthreads();
+    double2* x = a;
+    a = b;
+    b = x;
+    ns *= R;
+  }
+  for (int j = threadIdx.x; j < M; j += blockDim.x) p[(long long)j * inner] = a[j];
 }
 
 __global__ void load_rho_kernel(double2* data, Grid3 g, const double* rho, Grid3 n)
@@ -724,6 +794,9 @@ hipError_t launch_twiddles(double2* w, int M, hipStream_t s)
   return hipGetLastError();
 }
 
+// The transform of every line along one axis: the mixed-radix FFT when the
+// length factors into 4s, 2s and 3s (all lengths this library accepts), else
+// the direct sum.
 hipError_t launch_dft_axis(double2* data, Grid3 g, int axis, int sign, const double2* tw, hipStream_t s)
 {
   long long inner = 1;
@@ -732,8 +805,27 @@ hipError_t launch_dft_axis(double2* data, Grid3 g, int axis, int sign, const dou
   const int M = g.m[axis];
   const long long lines = tot / M;
   if (M == 1) return hipSuccess;
-  const size_t lds = 2 * (size_t)M * sizeof(double2);
-  hipLaunchKernelGGL(dft_kernel, dim3((unsigned)lines), dim3(128), lds, s, data, inner, M, sign, tw);
+  FftPlan plan{};
+  int m = M;
+  while (m % 4 == 0 && plan.n < 24) {
+    plan.r[plan.n++] = 4;
+    m /= 4;
+  }
+  while (m % 2 == 0 && plan.n < 24) {
+    plan.r[plan.n++] = 2;
+    m /= 2;
+  }
+  while (m % 3 == 0 && plan.n < 24) {
+    plan.r[plan.n++] = 3;
+    m /= 3;
+  }
+  if (m == 1) {
+    const size_t lds = 3 * (size_t)M * sizeof(double2);
+    hipLaunchKernelGGL(fft_kernel, dim3((unsigned)lines), dim3(128), lds, s, data, inner, M, sign, tw, plan);
+  } else {
+    const size_t lds = 2 * (size_t)M * sizeof(double2);
+    hipLaunchKernelGGL(dft_kernel, dim3((unsigned)lines), dim3(128), lds, s, data, inner, M, sign, tw);
+  }
   return hipGetLastError();
 }
 
