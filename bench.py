@@ -173,12 +173,12 @@ def kernel_name(phase, w, elem_bytes):
             return "vp::kick_pair_block<double, 32, 0, 8>"   # first of the three quarter-block passes
         return "vp::kick_pair_block<%s, %d, 2, %d>" % (t, w.nv[0], plane_slices(w, elem_bytes))
     if phase == "drift_yz":
-        # one line per lane: (velocity cells per chunk, tiles per workgroup,
-        # chunks per cache line); two lines per lane: (cells per chunk, tiles)
+        # (velocity cells per chunk, tiles per workgroup, chunks per cache line)
+        # of the one-line-per-lane and the two-lines-per-lane kernels
         one = {16: (64, 4, 1), 24: (32, 4, 1)} if elem_bytes == 4 else {16: (32, 2, 1), 24: (16, 2, 1), 48: (8, 2, 2)}
-        two = {32: (32, 4), 48: (32, 4), 64: (16, 4)} if elem_bytes == 4 else {32: (16, 4)}
+        two = {32: (32, 4, 1), 48: (32, 4, 1), 64: (16, 4, 2)} if elem_bytes == 4 else {32: (16, 4, 1)}
         if w.n[1] in two:
-            return "vp::drift_yz_pairs<%s, %d, %d, %d>" % ((t, w.n[1]) + two[w.n[1]])
+            return "vp::drift_yz_pairs<%s, %d, %d, %d, %d>" % ((t, w.n[1]) + two[w.n[1]])
         return "vp::drift_yz_block<%s, %d, %d, %d, %d, %d>" % ((t, w.n[1], w.n[2]) + one[w.n[1]])
     axis = ["x", "y", "z", "vx", "vy", "vz"].index(phase)
     n = (list(w.n) + list(w.nv))[axis]
