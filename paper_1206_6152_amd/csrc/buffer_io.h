@@ -45,6 +45,12 @@ __device__ __forceinline__ void buf_store<double>(__amdgpu_buffer_rsrc_t r, unsi
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, x), r, voff, soff, 0);
 }
 
+// 8 bytes: the values of two adjacent FP32 cells
+__device__ __forceinline__ float2 buf_load_pair(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
 // 16 bytes: four floats or two doubles. The whole offset is per lane and the
 // uniform offset field is the constant 0: with a register there, the
 // compiler's check for the hazard of a store wider than 8 bytes whose data

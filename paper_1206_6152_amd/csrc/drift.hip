@@ -5,6 +5,7 @@
 #include "vp_internal.h"
 
 #include "pfc_line.h"
+#include "vec16.h"
 
 namespace vp {
 namespace {
@@ -192,17 +193,6 @@ struct DrPairShape {
   static constexpr int BYTES = ELEMS * (int)sizeof(T);
   static constexpr int THREADS = NP * H;
   static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && THREADS % 64 == 0 && W % 2 == 0;
-};
-
-template <typename T>
-struct Pair2;
-template <>
-struct Pair2<float> {
-  using type = float2;
-};
-template <>
-struct Pair2<double> {
-  using type = double2;
 };
 
 template <typename T, int NP, int W, int TILES, int G>

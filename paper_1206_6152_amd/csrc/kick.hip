@@ -382,6 +382,105 @@ __global__ __launch_bounds__((PairShape<T, NV, PASS, CH_>::THREADS)) void kick_p
   }
 }
 
+// ---- T_vx then T_vy with two lines per lane, on vz-slices of W cells ---------
+// The first of the three slice passes for blocks whose vz-slices of the layout
+// above would hold only 32-byte runs (64^3 FP32: 8 values). Lane (i, p) of the
+// NV x W/2 lanes holds the lines of the adjacent vz cells 2p and 2p + 1 of the
+// slice: the vx lines (vy = i) come in as 8-byte pairs, so that a row of W/2
+// lanes reads one whole W-cell run (64 bytes), in the sweep's orientation, and
+// are swept in registers. They reach the vy sweep through LDS in two rounds
+// (cells 2p, then 2p + 1) of W/2 columns each, parked at their storage vx and
+// at the vy place of the vy sweep's orientation; lane (i, p) then takes the vy
+// lines (vx = i) of the same two cells, which go back to HBM as pairs. All
+// lines of a block share the spatial cell's coefficients, shifts and
+// orientations. The slices of a block share cache lines and are grouped per
+// XCD as in kick_pair_block.
+template <typename T, int NV, int W>
+struct KvPairShape {
+  static constexpr int H = W / 2;                                   // LDS columns per round
+  static constexpr int SX0 = NV * H;
+  static constexpr int SX = SX0 + ((((H - SX0) % 64) + 64) % 64);   // = H (mod 64)
+  static constexpr int ELEMS = NV * SX;
+  static constexpr int BYTES = ELEMS * (int)sizeof(T);
+  static constexpr int THREADS = NV * H;
+  static constexpr int NCH = NV / W;
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && THREADS % 64 == 0 && NV % W == 0;
+};
+
+// One round of kick_vxvy_pairs: the lane's swept vx line goes to LDS at its
+// storage vx places and at the vy place of the vy sweep's orientation; after
+// the barrier the lane takes the vy line of storage vx = i0 of the same cell
+// and sweeps it.
+template <typename T, int NV, int W>
+__device__ __forceinline__ void kv_round(T (&v)[NV], T* L, int i0, int p, bool fx, bool fy,
+                                         const KickTab<T>* __restrict__ tab)
+{
+  using S = KvPairShape<T, NV, W>;
+  constexpr int H = S::H;
+  const int yb = (fy ? NV - 1 - i0 : i0) * H + p;
+  store_shifted<T, NV>(v, tab->shift[0], false, [&](int d, T x) { L[(fx ? NV - 1 - d : d) * S::SX + yb] = x; });
+  __syncthreads();
+  const int xb = i0 * S::SX + p;
+#pragma unroll
+  for (int r = 0; r < NV; r++) v[r] = L[xb + r * H];
+  pfc_core<T, NV>(v, tab->alpha[1], tab->c1[1], tab->c2[1], false);
+  __syncthreads();  // LDS is reused by the next round
+}
+
+template <typename T, int NV, int W>
+__global__ __launch_bounds__((KvPairShape<T, NV, W>::THREADS)) void kick_vxvy_pairs(KickArgs a)
+{
+  static_assert(sizeof(T) == 4, "8-byte pairs of FP32 cells");
+  using S = KvPairShape<T, NV, W>;
+  constexpr int H = S::H;
+  constexpr unsigned PLANEB = NV * NV * 4u, ROWB = NV * 4u, BLKB = NV * PLANEB;
+  __shared__ T L[S::ELEMS];
+  const int tid = threadIdx.x;
+  const int i0 = tid / H, p = tid - i0 * H;
+  long long s;
+  int slice;
+  if (a.xcd_group) {
+    const long long b = blockIdx.x, x = b & 7, k = b >> 3, m = k / S::NCH;
+    slice = (int)(k - m * S::NCH);
+    s = 8 * m + x;
+  } else {
+    s = blockIdx.x / S::NCH;
+    slice = (int)(blockIdx.x - s * S::NCH);
+  }
+  const auto rs = buf_rsrc(static_cast<const T*>(a.f) + s * (long long)(NV * NV * NV), BLKB);
+  const unsigned cofs = (unsigned)(slice * W + 2 * p) * 4u;   // the pair's vz cells, bytes
+  const KickTab<T>* __restrict__ tab = static_cast<const KickTab<T>*>(a.tab) + s;
+  const bool fx = tab_neg(tab->neg, 0), fy = tab_neg(tab->neg, 1);
+  T v0[NV], v1[NV];
+  {
+    // vx lines (vy = i0), rows read in the sweep's orientation
+    const unsigned voff = (unsigned)i0 * ROWB + cofs;
+#pragma unroll
+    for (int r = 0; r < NV; r++) {
+      const float2 x = buf_load_pair(rs, voff, (unsigned)(fx ? NV - 1 - r : r) * PLANEB);
+      v0[r] = x.x;
+      v1[r] = x.y;
+    }
+  }
+  pfc_core<T, NV>(v0, tab->alpha[0], tab->c1[0], tab->c2[0], false);
+  pfc_core<T, NV>(v1, tab->alpha[0], tab->c1[0], tab->c2[0], false);
+  kv_round<T, NV, W>(v0, L, i0, p, fx, fy, tab);
+  kv_round<T, NV, W>(v1, L, i0, p, fx, fy, tab);
+  // sweep place d of a vy line (vx = i0) is storage vy = d, or NV-1-d where a_y < 0
+  char* wb = static_cast<char*>(a.f) + s * (long long)BLKB + (unsigned)i0 * PLANEB + cofs;
+  store_shifted2<T, NV>(v0, v1, tab->shift[1], false, [&](int d, T x0, T x1) {
+    *reinterpret_cast<float2*>(wb + (unsigned)(fy ? NV - 1 - d : d) * ROWB) = float2{x0, x1};
+  });
+}
+
+// vz-slice width of the two-lines-per-lane T_vx T_vy pass, or 0 where the
+// slices of kick_pair_block already hold whole 64-byte runs
+template <typename T, int NV>
+constexpr int vxvy_pair_width()
+{
+  return (sizeof(T) == 4 && NV == 64) ? 16 : 0;
+}
+
 // The three two-sweep passes of two consecutive half kicks (T_vx T_vy on
 // slices of CV vz-planes, T_vz T_vx on slices of CY vy-rows, T_vy T_vz on
 // slices of CX vx-planes) for velocity blocks whose halves exceed the LDS:
@@ -401,8 +500,15 @@ hipError_t launch_kick_slices(const KickArgs& a0, int pass, hipStream_t s)
   a.xcd_group = (a.np % 8 == 0) ? 1 : 0;
   switch (pass) {
     case 0:
-      hipLaunchKernelGGL((kick_pair_block<T, NV, 0, CV>), dim3((unsigned)(PairShape<T, NV, 0, CV>::NCH * a.np)),
-                         dim3(PairShape<T, NV, 0, CV>::THREADS), 0, s, a);
+      if constexpr (vxvy_pair_width<T, NV>() > 0) {
+        using K = KvPairShape<T, NV, vxvy_pair_width<T, NV>()>;
+        static_assert(K::fits, "slice does not fit the LDS");
+        hipLaunchKernelGGL((kick_vxvy_pairs<T, NV, vxvy_pair_width<T, NV>()>), dim3((unsigned)(K::NCH * a.np)),
+                           dim3(K::THREADS), 0, s, a);
+      } else {
+        hipLaunchKernelGGL((kick_pair_block<T, NV, 0, CV>), dim3((unsigned)(PairShape<T, NV, 0, CV>::NCH * a.np)),
+                           dim3(PairShape<T, NV, 0, CV>::THREADS), 0, s, a);
+      }
       break;
     case 1:
       hipLaunchKernelGGL((kick_pair_block<T, NV, 1, CY>), dim3((unsigned)(PairShape<T, NV, 1, CY>::NCH * a.np)),
