@@ -102,10 +102,21 @@ def copy_bandwidth(f):
     return nbytes / (ms * 1e-3) / 1e9
 
 
+def code_digest(path):
+    """sha256 of a C/C++/HIP source with its comments and all whitespace removed, so that
+    only a change of the code itself changes it (string literals hold no comment markers
+    in these sources)."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256(re.sub(r"\s+", "", text).encode()).hexdigest()
+
+
 def committed_traffic(w, elem_bytes, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when there is none or the kernel sources changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md"
                         % (w.name.replace("_", ""), "f32" if elem_bytes == 4 else "f64"))
     if not os.path.exists(path):
@@ -113,13 +124,14 @@ def committed_traffic(w, elem_bytes, kernel):
     digests, traffic = {}, {}
     for line in open(path):
         parts = line.split()
-        if len(parts) == 3 and parts[0] == "sha256":
+        if len(parts) == 3 and parts[0] == "code-sha256":
             digests[parts[2]] = parts[1]
         elif len(parts) >= 3 and parts[0] == "traffic_bytes":
             traffic[" ".join(parts[1:-1])] = float(parts[-1])
+    if not digests:
+        return None
     for rel, digest in digests.items():
-        cur = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()
-        if cur != digest:
+        if code_digest(os.path.join(ROOT, rel)) != digest:
             return None
     return traffic.get(kernel)
 

@@ -12,10 +12,12 @@ namespace {
 
 // ---- one-pass drift along z, then y -----------------------------------------
 // A tile is one x index and W consecutive velocity cells of every (y, z) cell
-// (W contiguous values per (y, z) cell in HBM, one or more whole cache lines).
-// Each z line of a tile is read from HBM by one lane, updated in registers and
-// parked in LDS; after a barrier each y line is taken from LDS by one lane,
-// updated and written back to HBM. f crosses HBM once for the two sweeps.
+// (W contiguous values per (y, z) cell in HBM). Each z line of a tile is read
+// from HBM by one lane, updated in registers and parked in LDS; after a
+// barrier each y line is taken from LDS by one lane, updated and written back
+// to HBM. f crosses HBM once for the two sweeps. Two kernels: drift_yz_block
+// below (one line per lane, the next tile's z lines prefetched) and
+// drift_yz_pairs further down (two lines per lane, half the LDS per tile).
 // Rows of W are unpadded; planes are padded to SY = W (mod 64) elements so
 // both sweep directions are bank-conflict free.
 //
@@ -78,8 +80,9 @@ __global__ __launch_bounds__(256) void drift_table_kernel(DriftArgs a)
   yt[j] = LineTab<T>{cy.alpha, cy.c1, cy.c2, (cy.shift & 0xffff) | flags};
 }
 
-// Chunks narrower than a 128-byte cache line (W sizeof(T) = 128 / G bytes,
-// the 48-cell planes) share each line among G consecutive chunks. A
+// Chunks narrower than a 128-byte cache line (W sizeof(T) = 128 / G bytes:
+// FP64 48-cell planes here, FP32 64-cell planes in drift_yz_pairs) share each
+// line among G consecutive chunks. A
 // unit is then G workgroups that take chunks (c TILES + t) G + q, q = 0..G-1,
 // tile by tile; with a.xcd_group the G workgroups of a unit are b = 8 (G m +
 // q) + x, which the round-robin over the 8 XCDs places on one XCD (x) one
@@ -323,10 +326,12 @@ hipError_t launch_drift_yz_sq(const DriftArgs& a0, hipStream_t s)
 }  // namespace
 
 // Velocity cells per chunk (W), tiles per workgroup, chunks per cache line (G)
-// and kernel of the one-pass T_z T_y. One line per lane (drift_yz_block):
-// whole-line chunks for 16- to 32-cell planes, half-line chunks for 48-cell
-// planes, whose workgroups are grouped per line (above). Two lines per lane
-// (drift_yz_pairs, nv_z even): 64-cell FP32 planes in 16-cell chunks.
+// and kernel of the one-pass T_z T_y. Two lines per lane (drift_yz_pairs,
+// nv_z even): FP32 planes of 32 and 48 cells and FP64 planes of 32 in
+// whole-line chunks, FP32 64-cell planes in half-line chunks grouped per line.
+// One line per lane (drift_yz_block): whole-line chunks for 16- and 24-cell
+// planes, half-line chunks grouped per line for FP64 48-cell planes. FP64
+// 64-cell planes, and the rest, take the single sweeps.
 struct DriftPlan {
   int w, tiles, g, pairs;
 };

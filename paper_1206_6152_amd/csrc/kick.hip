@@ -573,9 +573,9 @@ hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hip
   return nv[0] == 48 ? launch_kick_planes<double, 48, 6>(a, s) : launch_kick_planes<double, 64, 4>(a, s);
 }
 
-// 48^3 and 64^3 FP32 blocks: vz-slices of 16 and 8 planes, vy-slices of 16
-// and 8 rows, vx-slices of 12 and 8 planes (147, 150, 110 KiB; 128, 130,
-// 130 KiB)
+// 48^3 and 64^3 FP32 blocks: vz-slices of 16 planes (48^3; 147 KiB) or the
+// two-lines-per-lane pass on 16-cell vz-slices (64^3; 130 KiB), vy-slices of
+// 16 and 8 rows, vx-slices of 12 and 8 planes (150, 110 KiB; 130, 130 KiB)
 bool kick_slices_supported(int dtype, const int nv[3])
 {
   return dtype == 0 && nv[0] == nv[1] && nv[1] == nv[2] && (nv[0] == 48 || nv[0] == 64);
