@@ -20,6 +20,7 @@
 // A velocity sweep's nu = a_l(x) tau / dv_l sends lam_nu to the acceleration;
 // the per-line values are reduced per spatial cell in a fixed order.
 #include "pfc_line.h"
+#include "vec16.h"
 #include "vp_internal.h"
 
 namespace vp {
@@ -311,6 +312,139 @@ __global__ __launch_bounds__(256) void reduce_lines_kernel(double* lam_a, const 
   if (threadIdx.x == 0) lam_a[s] += scale * sh[0];
 }
 
+// ---- reverse of one half kick in one pass --------------------------------------
+// The adjoint of T_vz T_vy T_vx (tau) for velocity blocks of which two copies
+// fit the LDS: the block's forward input x and its adjoint lam are staged
+// (16-byte loads, storage order, rows padded to N + 1 and planes to
+// SX = N (mod 64)); the forward states the reverse sweeps need are rebuilt in
+// LDS with the forward line update, and the reverse line updates run in
+// place on lam:
+//   B = T_vy T_vx x;  lam <- vz reverse at B;
+//   B = T_vx x;       lam <- vy reverse at B;
+//   B = x;            lam <- vx reverse at B;
+// then lam goes back to HBM. x crosses HBM up to three times (the reloads
+// mostly hit in L2) and lam twice, against twelve passes for two regenerated
+// states and three separate reverse sweeps. Each reverse line runs adj_line
+// on the same inputs as the single reverse sweep, and the per-line nu
+// adjoints are added per axis in the order of reduce_lines_kernel, so the
+// results are those of the separate passes bit for bit.
+template <typename T, int N>
+struct AdjKickShape {
+  static constexpr int SY = N + 1;
+  static constexpr int SX0 = N * SY;
+  static constexpr int SX = SX0 + ((((N - SX0) % 64) + 64) % 64);
+  static constexpr int ELEMS = N * SX;
+  static constexpr int LINES = N * N;
+  // at least 256 lanes: the reduction below runs the 256-lane tree of reduce_lines_kernel
+  static constexpr int THREADS = (LINES + 63) / 64 * 64 > 256 ? (LINES + 63) / 64 * 64 : 256;
+  static constexpr int BYTES = 2 * ELEMS * (int)sizeof(T) + 3 * LINES * (int)sizeof(double) + 256 * (int)sizeof(double);
+  static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && N % (16 / (int)sizeof(T)) == 0;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(KickAdjArgs a)
+{
+  using S = AdjKickShape<T, N>;
+  using VT = typename Vec16<T>::type;
+  constexpr int V = Vec16<T>::n;
+  constexpr int NVEC = N * N * N / V;
+  __shared__ T B[S::ELEMS];
+  __shared__ T C[S::ELEMS];
+  __shared__ double dn[3][S::LINES];
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  const long long s = blockIdx.x;
+  const T* xg = static_cast<const T*>(a.fin) + s * (long long)(N * N * N);
+  T* lg = static_cast<T*>(a.lam) + s * (long long)(N * N * N);
+  const double nux = a.accel[0][s] * a.scale[0], nuy = a.accel[1][s] * a.scale[1], nuz = a.accel[2][s] * a.scale[2];
+  auto place = [](int e) {   // storage element e -> LDS index
+    const int jz = e % N, jy = (e / N) % N, jx = e / (N * N);
+    return jx * S::SX + jy * S::SY + jz;
+  };
+  auto stage = [&](T* dst, const T* src) {
+    for (int k = tid; k < NVEC; k += S::THREADS) {
+      const VT x = reinterpret_cast<const VT*>(src)[k];
+      const int b = place(k * V);
+#pragma unroll
+      for (int q = 0; q < V; q++) dst[b + q] = lane_of<VT, T>(x, q);
+    }
+  };
+  // forward sweep of B along vx (lanes (jy, jz)) or vy (lanes (jx, jz)), in place
+  auto forward = [&](int axis, double nu) {
+    if (tid < S::LINES) {
+      const int o = tid / N, i = tid - o * N;
+      const int base = axis == 0 ? o * S::SY + i : o * S::SX + i;
+      const int st = axis == 0 ? S::SX : S::SY;
+      T v[N];
+#pragma unroll
+      for (int r = 0; r < N; r++) v[r] = B[base + r * st];
+      const LineCoef<T> k = pfc_line<T, N>(v, nu, false);
+      store_shifted<T, N>(v, k.shift, false, [&](int r, T x) { B[base + r * st] = x; });
+    }
+    __syncthreads();
+  };
+  // reverse sweep along `axis` at forward input B, lam in C, in place
+  auto reverse = [&](int axis, double nu) {
+    if (tid < S::LINES) {
+      const int o = tid / N, i = tid - o * N;
+      int base, st;
+      if (axis == 2) { base = o * S::SX + i * S::SY; st = 1; }          // vz lines, lanes (jx, jy)
+      else if (axis == 1) { base = o * S::SX + i; st = S::SY; }        // vy lines, lanes (jx, jz)
+      else { base = o * S::SY + i; st = S::SX; }                      // vx lines, lanes (jy, jz)
+      dn[axis][tid] = adj_line<T, N>(B, C, nu, false, [&](int r) { return base + r * st; });
+    }
+    __syncthreads();
+  };
+  stage(B, xg);
+  stage(C, lg);
+  __syncthreads();
+  forward(0, nux);
+  forward(1, nuy);
+  reverse(2, nuz);
+  stage(B, xg);
+  __syncthreads();
+  forward(0, nux);
+  reverse(1, nuy);
+  stage(B, xg);
+  __syncthreads();
+  reverse(0, nux);
+  for (int k = tid; k < NVEC; k += S::THREADS) {
+    const int b = place(k * V);
+    VT x;
+    T* xs = reinterpret_cast<T*>(&x);
+#pragma unroll
+    for (int q = 0; q < V; q++) xs[q] = C[b + q];
+    reinterpret_cast<VT*>(lg)[k] = x;
+  }
+  // lam_a[l][s] += scale_l * sum of the block's line adjoints, in the order of
+  // reduce_lines_kernel: lane t < 256 adds lines t, t + 256, ..., then a tree
+#pragma unroll
+  for (int l = 0; l < 3; l++) {
+    if (tid < 256) {
+      double acc = 0.0;
+      for (int i = tid; i < S::LINES; i += 256) acc += dn[l][i];
+      sh[tid] = acc;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) sh[tid] += sh[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) a.lam_a[l][s] += a.scale[l] * sh[0];
+    __syncthreads();
+  }
+}
+
+template <typename T, int N>
+hipError_t launch_kick_adj_n(const KickAdjArgs& a, hipStream_t s)
+{
+  using S = AdjKickShape<T, N>;
+  static_assert(S::fits, "two velocity blocks do not fit the LDS");
+  if (a.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL((kick_adj_block<T, N>), dim3((unsigned)a.np), dim3(S::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int N>
 hipError_t launch_adj_n(const SweepArgs& a, const void* fin, void* lam, double* dnu, hipStream_t s)
 {
@@ -369,6 +503,29 @@ hipError_t launch_sweep_adjoint(const SweepArgs& a, int dtype, const void* fin, 
                                 hipStream_t s)
 {
   return dtype == 0 ? launch_adj_t<float>(a, fin, lam, dnu, s) : launch_adj_t<double>(a, fin, lam, dnu, s);
+}
+
+// Cubic velocity blocks of which two copies fit the LDS: FP32 8^3, 16^3,
+// 24^3; FP64 8^3 (FP64 16^3 fits too, but its reverse lines need more
+// registers than a lane has and spill).
+bool kick_adjoint_supported(int dtype, const int nv[3])
+{
+  if (nv[0] != nv[1] || nv[1] != nv[2]) return false;
+  const int n = nv[0];
+  return n == 8 || (dtype == 0 && (n == 16 || n == 24));
+}
+
+hipError_t launch_kick_adjoint(const KickAdjArgs& a, int dtype, const int nv[3], hipStream_t s)
+{
+  if (!kick_adjoint_supported(dtype, nv)) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    switch (nv[0]) {
+      case 8: return launch_kick_adj_n<float, 8>(a, s);
+      case 16: return launch_kick_adj_n<float, 16>(a, s);
+      default: return launch_kick_adj_n<float, 24>(a, s);
+    }
+  }
+  return launch_kick_adj_n<double, 8>(a, s);
 }
 
 hipError_t launch_reduce_lines(double* lam_a, const double* dnu, long long np, long long per, double scale,

@@ -449,6 +449,25 @@ int sweep_adjoint(vp_ctx* c, int axis, double tau, const void* fin, void* lam, d
   return VP_OK;
 }
 
+// lam <- adjoint of the half kick T_vz T_vy T_vx (tau) at forward input fin,
+// with c->accel, in one pass; lam_a[l] gains the acceleration adjoint
+int kick_adjoint(vp_ctx* c, double tau, const void* fin, void* lam, double* lam_a)
+{
+  vp::KickAdjArgs a{};
+  a.fin = fin;
+  a.lam = lam;
+  a.np = c->np;
+  for (int l = 0; l < 3; l++) {
+    a.accel[l] = c->accel + (long long)l * c->np;
+    a.scale[l] = tau / c->dv[l];
+    a.lam_a[l] = lam_a + (long long)l * c->np;
+  }
+  const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
+  PhaseScope scope(c, 10);
+  LAUNCH(c, vp::launch_kick_adjoint(a, c->cfg.dtype, nv, c->stream));
+  return VP_OK;
+}
+
 // c->radj = G^T D^T lam_a: transpose of potential -> acceleration, per spatial
 // cell (the density adjoint; lam then gains dv^3 times it)
 int density_adjoint(vp_ctx* c, const double* lam_a)
@@ -1057,7 +1076,11 @@ int sweep_on(vp_ctx* c, int axis, double tau, void* buf)
 //   opening half kick (a_n):      in1 = T_vx x0 and in2 = T_vy in1.
 // Every regenerated input is computed by the kernels of the forward run, so it
 // is the forward input bit for bit; the price is twelve sweep passes per step
-// instead of eight.
+// instead of eight. Where two velocity blocks fit the LDS
+// (kick_adjoint_supported), each reverse half kick is one pass at its input
+// (in6, or x0) that rebuilds in7, in8 (in1, in2) on chip: seven regenerating
+// passes and five reverse passes per step instead of twelve and nine, with the
+// same bits.
 int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
 {
   const size_t fb = (size_t)c->np * (size_t)c->nv3 * (c->cfg.dtype == VP_F32 ? 4 : 8);
@@ -1078,6 +1101,8 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
   if ((r = w.f(&b1, fb)) || (r = w.f(&b2, fb))) return r;
   if ((r = w.d(&ahist, ab * (size_t)(nsteps + 1))) || (r = w.d(&lam_a, ab)) || (r = w.d(&lam_p, ab))) return r;
   auto A = [&](int n) { return ahist + (size_t)n * 3 * c->np; };
+  const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
+  const bool fused_adj = vp::kick_adjoint_supported(c->cfg.dtype, nv);
   auto set_accel = [&](int n) { return copy_f(c, c->accel, A(n), ab); };
 
   // forward pass from f0, keeping checkpoints and every step's acceleration
@@ -1116,13 +1141,18 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
     for (int n = s1 - 1; n >= s0 && r == VP_OK; n--) {
       void* x0 = st[n - s0];
       // closing half kick, acceleration a_{n+1}: in6 in b1, in8 then in7 in b2
+      // (or the whole reverse half kick in one pass at in6)
       if ((r = set_accel(n)) || (r = kick_to(c, h, x0, b1, fb))) break;
       if ((r = drift(c, dt))) break;                                     // b1 = in6
-      if ((r = set_accel(n + 1)) || (r = sweep_to(c, 3, h, b1, b2)) || (r = sweep_on(c, 4, h, b2))) break;
-      if ((r = copy_f(c, lam_a, lam_p, ab))) break;
-      if ((r = sweep_adjoint(c, 5, h, b2, lam, lam_a))) break;            // at in8
-      if ((r = sweep_to(c, 3, h, b1, b2)) || (r = sweep_adjoint(c, 4, h, b2, lam, lam_a))) break;   // at in7
-      if ((r = sweep_adjoint(c, 3, h, b1, lam, lam_a))) break;            // at in6
+      if ((r = set_accel(n + 1)) || (r = copy_f(c, lam_a, lam_p, ab))) break;
+      if (fused_adj) {
+        if ((r = kick_adjoint(c, h, b1, lam, lam_a))) break;
+      } else {
+        if ((r = sweep_to(c, 3, h, b1, b2)) || (r = sweep_on(c, 4, h, b2))) break;
+        if ((r = sweep_adjoint(c, 5, h, b2, lam, lam_a))) break;          // at in8
+        if ((r = sweep_to(c, 3, h, b1, b2)) || (r = sweep_adjoint(c, 4, h, b2, lam, lam_a))) break;   // at in7
+        if ((r = sweep_adjoint(c, 3, h, b1, lam, lam_a))) break;          // at in6
+      }
       // a_{n+1} = A(state after the drift): the density adjoint's contribution
       // to lam rides on the loads of the reverse x sweep that follows
       if ((r = density_adjoint(c, lam_a))) break;
@@ -1132,8 +1162,12 @@ int grad_impl(vp_ctx* c, int nsteps, double dt, int k, void* lam, double* loss)
       if ((r = sweep_adjoint(c, 0, dt, b2, lam, nullptr, c->radj))) break;
       if ((r = sweep_to(c, 2, dt, b1, b2)) || (r = sweep_adjoint(c, 1, dt, b2, lam, nullptr))) break;   // at in4
       if ((r = sweep_adjoint(c, 2, dt, b1, lam, nullptr))) break;         // at in3
-      // opening half kick, acceleration a_n: in1 in b1, in2 in b2
+      // opening half kick, acceleration a_n: in1 in b1, in2 in b2 (or one pass at x0)
       HIP_TRY(hipMemsetAsync(lam_p, 0, ab, c->stream));
+      if (fused_adj) {
+        if ((r = kick_adjoint(c, h, x0, lam, lam_p))) break;
+        continue;
+      }
       if ((r = sweep_to(c, 3, h, x0, b1)) || (r = sweep_to(c, 4, h, b1, b2))) break;
       if ((r = sweep_adjoint(c, 5, h, b2, lam, lam_p)) || (r = sweep_adjoint(c, 4, h, b1, lam, lam_p)) ||
           (r = sweep_adjoint(c, 3, h, x0, lam, lam_p)))

@@ -200,6 +200,19 @@ hipError_t launch_sweep_adjoint(const SweepArgs& a, int dtype, const void* fin, 
                                 hipStream_t s);
 bool adjoint_addend_supported(const SweepArgs& a);
 // lam_a[s] += scale * sum_{i < per} dnu[s*per + i], s < np
+// Reverse of one half kick T_vz T_vy T_vx in one pass (see adjoint.hip): lam
+// <- J^T lam at forward input fin, and lam_a[l][s] += scale[l] * (the block's
+// summed line adjoints), for the grids kick_adjoint_supported accepts.
+struct KickAdjArgs {
+  const void* fin;
+  void* lam;
+  long long np;
+  const double* accel[3];
+  double scale[3];    // tau / dv_l
+  double* lam_a[3];
+};
+bool kick_adjoint_supported(int dtype, const int nv[3]);
+hipError_t launch_kick_adjoint(const KickAdjArgs& a, int dtype, const int nv[3], hipStream_t s);
 hipError_t launch_reduce_lines(double* lam_a, const double* dnu, long long np, long long per, double scale,
                                hipStream_t s);
 hipError_t launch_gradient_adj(double* lphi_ext, const double* lam_a, Grid3 n, double d0, double d1, double d2,
