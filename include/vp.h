@@ -215,6 +215,15 @@ double vp_cell_self_integral(double dx, double dy, double dz);
  * is not NULL, the adjoint of the stored acceleration component a_{axis-3} is
  * added to it (the sweep moves with nu = a tau / dv).
  *
+ * vp_kick_adjoint: lam <- J^T lam for the half kick T_vz T_vy T_vx (tau) of
+ * Eq. (17) with the stored acceleration, taken at the forward input f_in
+ * (arguments as for vp_sweep_adjoint; lam_accel, when not NULL, gains the
+ * adjoint of all three acceleration components). One pass per velocity
+ * block that rebuilds the two intermediate states on chip; the result equals
+ * vp_sweep_adjoint along vz, vy and vx at those states bit for bit. Available
+ * where two velocity blocks fit on chip (cubic grids of 8, 16 or 24 cells in
+ * VP_F32, 8 in VP_F64); VP_EUNSUPPORTED elsewhere, before any device work.
+ *
  * vp_accel_adjoint: lam += dv^3 G^T D^T lam_accel, the transpose of the linear
  * map f -> density -> potential -> acceleration of Eqs. (18)-(22).
  *
@@ -231,6 +240,7 @@ double vp_cell_self_integral(double dx, double dy, double dz);
  * returning (VP_ENOMEM if they do not fit). Synchronises the stream. */
 int vp_sweep_adjoint(vp_ctx* ctx, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,
                      double* lam_accel_dev);
+int vp_kick_adjoint(vp_ctx* ctx, double tau, const void* f_in_dev, void* lam_dev, double* lam_accel_dev);
 int vp_accel_adjoint(vp_ctx* ctx, const double* lam_accel_dev, void* lam_dev);
 int vp_grad(vp_ctx* ctx, int32_t nsteps, double dt, int32_t ckpt_every, void* grad_f0_dev, double* loss_host);
 

@@ -13,7 +13,7 @@ from ._lib import (VP_BC_ISOLATED, VP_BC_PERIODIC, VP_F32, VP_F64, VPError, make
                    vp_accel, vp_config_validate, vp_density, vp_drift, vp_dt, vp_energy, vp_free, vp_kick,
                    vp_get_accel, vp_init, vp_last_error, vp_potential, vp_profile_enable,
                    vp_profile_read, vp_run, vp_set_accel, vp_step, vp_sweep, vp_sweep_adjoint,
-                   vp_accel_adjoint, vp_grad, vp_moment)
+                   vp_kick_adjoint, vp_accel_adjoint, vp_grad, vp_moment)
 
 __all__ = ["Simulator", "VPError", "make_config", "config_of", "VP_F32", "VP_F64",
            "VP_BC_PERIODIC", "VP_BC_ISOLATED", "vp_init", "vp_step", "vp_run", "vp_sweep",
@@ -114,6 +114,11 @@ class Simulator:
         """lam <- J^T lam for T_axis(tau) at forward input f_in (tensors like f)."""
         vp_sweep_adjoint(self.ctx, axis, tau, f_in.data_ptr(), lam.data_ptr(),
                          lam_accel.data_ptr() if lam_accel is not None else 0)
+
+    def kick_adjoint(self, tau: float, f_in, lam, lam_accel=None):
+        """lam <- J^T lam for the half kick T_vz T_vy T_vx(tau) at forward input f_in."""
+        vp_kick_adjoint(self.ctx, tau, f_in.data_ptr(), lam.data_ptr(),
+                        lam_accel.data_ptr() if lam_accel is not None else 0)
 
     def accel_adjoint(self, lam_accel, lam):
         vp_accel_adjoint(self.ctx, lam_accel.data_ptr(), lam.data_ptr())

@@ -32,7 +32,7 @@ ERROR_NAMES = {VP_EINVAL: "VP_EINVAL", VP_ENOMEM: "VP_ENOMEM", VP_EHIP: "VP_EHIP
 EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run", "vp_sweep",
            "vp_kick", "vp_drift",
            "vp_accel", "vp_get_accel", "vp_set_accel", "vp_density", "vp_moment", "vp_potential", "vp_energy",
-           "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_accel_adjoint",
+           "vp_dt", "vp_profile_enable", "vp_profile_read", "vp_sweep_adjoint", "vp_kick_adjoint", "vp_accel_adjoint",
            "vp_grad", "vp_stream_copy", "vp_cell_self_integral", "vp_sweep_adjoint_noalloc", "vp_free",
            "vp_last_error"]
 VP_NOALLOC_MAX_LINES = 4194304
@@ -100,6 +100,7 @@ def lib():
             "vp_profile_enable": [P, i32],
             "vp_profile_read": [P, D, ctypes.POINTER(ctypes.c_int64)],
             "vp_sweep_adjoint": [P, i32, f64, P, P, P],
+            "vp_kick_adjoint": [P, f64, P, P, P],
             "vp_sweep_adjoint_noalloc": [P, i32, f64, P, P, P],
             "vp_accel_adjoint": [P, P, P],
             "vp_grad": [P, i32, f64, i32, P, D],
@@ -234,6 +235,11 @@ def vp_profile_read(ctx: int):
 def vp_sweep_adjoint(ctx: int, axis: int, tau: float, fin_ptr: int, lam_ptr: int, lam_accel_ptr: int = 0) -> None:
     check(lib().vp_sweep_adjoint(ctx, int(axis), float(tau), ctypes.c_void_p(fin_ptr), ctypes.c_void_p(lam_ptr),
                                  ctypes.c_void_p(lam_accel_ptr or None)))
+
+
+def vp_kick_adjoint(ctx: int, tau: float, fin_ptr: int, lam_ptr: int, lam_accel_ptr: int = 0) -> None:
+    check(lib().vp_kick_adjoint(ctx, float(tau), ctypes.c_void_p(fin_ptr), ctypes.c_void_p(lam_ptr),
+                                ctypes.c_void_p(lam_accel_ptr or None)))
 
 
 def vp_sweep_adjoint_noalloc(ctx: int, axis: int, tau: float, fin_ptr: int, lam_ptr: int,

@@ -418,6 +418,7 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
   }
   // lam_a[l][s] += scale_l * sum of the block's line adjoints, in the order of
   // reduce_lines_kernel: lane t < 256 adds lines t, t + 256, ..., then a tree
+  if (!a.lam_a[0]) return;   // uniform: no acceleration adjoint wanted
 #pragma unroll
   for (int l = 0; l < 3; l++) {
     if (tid < 256) {

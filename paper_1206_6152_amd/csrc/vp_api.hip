@@ -460,7 +460,7 @@ int kick_adjoint(vp_ctx* c, double tau, const void* fin, void* lam, double* lam_
   for (int l = 0; l < 3; l++) {
     a.accel[l] = c->accel + (long long)l * c->np;
     a.scale[l] = tau / c->dv[l];
-    a.lam_a[l] = lam_a + (long long)l * c->np;
+    a.lam_a[l] = lam_a ? lam_a + (long long)l * c->np : nullptr;
   }
   const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
   PhaseScope scope(c, 10);
@@ -960,6 +960,19 @@ int vp_sweep_adjoint(vp_ctx* c, int32_t axis, double tau, const void* f_in_dev, 
   if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
   if (!f_in_dev || !lam_dev) return fail(VP_EINVAL, "null pointer");
   return sweep_adjoint(c, axis, tau, f_in_dev, lam_dev, lam_accel_dev);
+}
+
+int vp_kick_adjoint(vp_ctx* c, double tau, const void* f_in_dev, void* lam_dev, double* lam_accel_dev)
+{
+  g_err.clear();
+  int r = check_ctx(c);
+  if (r) return r;
+  if (!std::isfinite(tau)) return fail(VP_EINVAL, "tau must be finite");
+  if (!f_in_dev || !lam_dev) return fail(VP_EINVAL, "null pointer");
+  const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
+  if (!vp::kick_adjoint_supported(c->cfg.dtype, nv))
+    return fail(VP_EUNSUPPORTED, "no one-pass reverse half kick for this velocity grid");
+  return kick_adjoint(c, tau, f_in_dev, lam_dev, lam_accel_dev);
 }
 
 int vp_sweep_adjoint_noalloc(vp_ctx* c, int32_t axis, double tau, const void* f_in_dev, void* lam_dev,

@@ -209,7 +209,7 @@ struct KickAdjArgs {
   long long np;
   const double* accel[3];
   double scale[3];    // tau / dv_l
-  double* lam_a[3];
+  double* lam_a[3];   // all NULL: no acceleration adjoint
 };
 bool kick_adjoint_supported(int dtype, const int nv[3]);
 hipError_t launch_kick_adjoint(const KickAdjArgs& a, int dtype, const int nv[3], hipStream_t s);

@@ -106,6 +106,7 @@ int main()
   expect("dt", vp_dt(nullptr, 0.5, &d1), VP_EINVAL);
   expect("sweep_adjoint", vp_sweep_adjoint(nullptr, 3, 0.1, nullptr, nullptr, nullptr), VP_EINVAL);
   expect("sweep_adjoint_noalloc", vp_sweep_adjoint_noalloc(nullptr, 3, 0.1, nullptr, nullptr, nullptr), VP_EINVAL);
+  expect("kick_adjoint", vp_kick_adjoint(nullptr, 0.1, nullptr, nullptr, nullptr), VP_EINVAL);
   expect("accel_adjoint", vp_accel_adjoint(nullptr, nullptr, nullptr), VP_EINVAL);
   expect("grad", vp_grad(nullptr, 2, 0.1, 1, nullptr, &d1), VP_EINVAL);
   expect("profile_enable", vp_profile_enable(nullptr, 1), VP_EINVAL);

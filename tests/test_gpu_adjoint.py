@@ -56,6 +56,57 @@ def test_sweep_adjoint_matches_oracle(axis, bc, dtype):
         assert rel_l1(la, ref_la) <= (1e-11 if dtype == VP_F64 else 1e-4)
 
 
+@pytest.mark.parametrize("dtype,nv", [(VP_F32, 8), (VP_F32, 16), (VP_F32, 24), (VP_F64, 8)])
+@pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
+def test_one_pass_reverse_kick_equals_three_reverse_sweeps(dtype, nv, bc):
+    # vp_kick_adjoint rebuilds T_vx x and T_vy T_vx x on chip and runs the
+    # three reverse line updates there: lam and the acceleration adjoint must
+    # be the bits of vp_sweep_adjoint along vz, vy and vx at those states.
+    # Accelerations of both signs, with whole-cell shifts (|nu| up to 2.3).
+    print("case", dtype, nv, bc, flush=True)
+    torch = _t()
+    w = small_workload(bc, n=(2, 3, 2), nv=(nv, nv, nv))
+    rng = np.random.default_rng(nv + 7 * bc)
+    x = (structured_f(w.shape, 60 + nv) + 0.01 + 1e-3 * rng.uniform(0, 1, w.shape)).astype(NP[dtype])
+    lam0 = rng.standard_normal(w.shape).astype(NP[dtype])
+    tau = 0.27
+    a = rng.uniform(-1, 1, (3,) + w.n) * 2.3 * np.array([w.dv(l) for l in range(3)]).reshape(3, 1, 1, 1) / tau
+    g = _dev(x)
+    sim = Simulator(config_of(w, dtype), g)
+    sim.set_accel(_dev(a))
+    sim.sweep(3, tau)
+    in1 = g.clone()
+    sim.sweep(4, tau)
+    in2 = g.clone()
+    lam_s = _dev(lam0)
+    la_s = torch.zeros((3,) + w.n, dtype=torch.float64, device="cuda:0")
+    sim.sweep_adjoint(5, tau, in2, lam_s, la_s)
+    sim.sweep_adjoint(4, tau, in1, lam_s, la_s)
+    sim.sweep_adjoint(3, tau, _dev(x), lam_s, la_s)
+    lam_f = _dev(lam0)
+    la_f = torch.zeros((3,) + w.n, dtype=torch.float64, device="cuda:0")
+    sim.kick_adjoint(tau, _dev(x), lam_f, la_f)
+    lam_n = _dev(lam0)
+    sim.kick_adjoint(tau, _dev(x), lam_n)          # no acceleration adjoint wanted
+    sim.close()
+    assert torch.equal(lam_f, lam_s)
+    assert torch.equal(la_f, la_s)
+    assert torch.equal(lam_n, lam_s)
+    assert float(la_s.abs().sum()) > 0
+
+
+def test_reverse_kick_unsupported_grid():
+    from paper_1206_6152_amd import VPError, _lib
+    torch = _t()
+    w = small_workload(VP_BC_PERIODIC, n=(2, 2, 2), nv=(32, 32, 32))
+    x = _dev(np.full(w.shape, 0.5, dtype=np.float32))
+    sim = Simulator(config_of(w, VP_F32), x)
+    with pytest.raises(VPError) as e:
+        sim.kick_adjoint(0.1, x, x.clone())
+    sim.close()
+    assert e.value.code == _lib.VP_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
 def test_accel_adjoint_matches_oracle(bc):
     w = small_workload(bc, n=(4, 6, 8), nv=(4, 3, 2))
