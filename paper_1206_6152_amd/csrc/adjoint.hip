@@ -337,7 +337,7 @@ struct AdjKickShape {
   static constexpr int LINES = N * N;
   // at least 256 lanes: the reduction below runs the 256-lane tree of reduce_lines_kernel
   static constexpr int THREADS = (LINES + 63) / 64 * 64 > 256 ? (LINES + 63) / 64 * 64 : 256;
-  static constexpr int BYTES = 2 * ELEMS * (int)sizeof(T) + 3 * LINES * (int)sizeof(double) + 256 * (int)sizeof(double);
+  static constexpr int BYTES = 2 * ELEMS * (int)sizeof(T) + 3 * LINES * (int)sizeof(double) + 3 * 256 * (int)sizeof(double);
   static constexpr bool fits = BYTES <= 160 * 1024 && THREADS <= 1024 && N % (16 / (int)sizeof(T)) == 0;
 };
 
@@ -351,7 +351,7 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
   __shared__ T B[S::ELEMS];
   __shared__ T C[S::ELEMS];
   __shared__ double dn[3][S::LINES];
-  __shared__ double sh[256];
+  __shared__ double sh[3][256];
   const int tid = threadIdx.x;
   const long long s = blockIdx.x;
   const T* xg = static_cast<const T*>(a.fin) + s * (long long)(N * N * N);
@@ -418,22 +418,25 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
   }
   // lam_a[l][s] += scale_l * sum of the block's line adjoints, in the order of
   // reduce_lines_kernel: lane t < 256 adds lines t, t + 256, ..., then a tree
+  // (the three axes' trees side by side, with the same pairs as each alone)
   if (!a.lam_a[0]) return;   // uniform: no acceleration adjoint wanted
+  if (tid < 256) {
 #pragma unroll
-  for (int l = 0; l < 3; l++) {
-    if (tid < 256) {
+    for (int l = 0; l < 3; l++) {
       double acc = 0.0;
       for (int i = tid; i < S::LINES; i += 256) acc += dn[l][i];
-      sh[tid] = acc;
+      sh[l][tid] = acc;
     }
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) sh[tid] += sh[tid + w];
-      __syncthreads();
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int l = 0; l < 3; l++) sh[l][tid] += sh[l][tid + w];
     }
-    if (tid == 0) a.lam_a[l][s] += a.scale[l] * sh[0];
     __syncthreads();
   }
+  if (tid < 3) a.lam_a[tid][s] += a.scale[tid] * sh[tid][0];
 }
 
 template <typename T, int N>
