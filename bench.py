@@ -243,7 +243,7 @@ def gpu_run(w, vp_dtype, steps, warmup):
     step_bytes = 19.0 * s * cells          # 9 sweeps x 2 + one density read
     # what a step of this build must move: every pass over f reads and writes it once
     passes = sum(n for k, (ms, n) in phases.items()
-                 if k not in ("gravity", "adjoint_sweep", "adjoint_gravity")) / max(1, steps)
+                 if k not in ("gravity", "adjoint_sweep", "adjoint_gravity", "adjoint_kick")) / max(1, steps)
     fused_bytes = passes * 2.0 * s * cells
     kname = kernel_name(dom, w, s)
     traffic = committed_traffic(w, s, kname)
@@ -314,13 +314,18 @@ def adjoint_run():
     cells, s = w.cells, 4
     del f, f0, g
     torch.cuda.empty_cache()
-    ms, n = phases["adjoint_sweep"]
+    # the reverse kernel with the most time: the separate reverse sweeps or the
+    # one-pass reverse half kicks; either reads the forward input and lam and
+    # writes lam once per launch (3s bytes per cell)
+    name, ms, n = max([("reverse PFC sweep (sweep_adj_kernel)",) + tuple(phases["adjoint_sweep"]),
+                       ("one-pass reverse half kick (kick_adj_block)",) + tuple(phases["adjoint_kick"])],
+                      key=lambda t: t[1])
     per = ms / n if n else 0.0
-    rev_bytes = 3.0 * s * cells               # read the forward input and lam, write lam
+    rev_bytes = 3.0 * s * cells
     gbps = rev_bytes / (per * 1e-3) / 1e9 if per else 0.0
     return dict(value=cells * w.steps / wall, unit="cell-updates/s (forward steps differentiated)",
                 workload=w.name, steps=w.steps, ckpt_every=k, ms_per_gradient=wall * 1e3, loss=loss,
-                roofline=dict(bound="hbm", kernel="reverse PFC sweep (sweep_adj_kernel)", achieved=gbps,
+                roofline=dict(bound="hbm", kernel=name, achieved=gbps,
                               peak=PEAK_HBM_GBPS, unit="GB/s", frac=gbps / PEAK_HBM_GBPS,
                               algorithmic_bytes_per_launch=rev_bytes, avg_launch_ms=per, launches=n),
                 phases_ms={k_: v[0] for k_, v in phases.items() if v[1]})

@@ -177,9 +177,9 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * one-pass T_y T_z, phase 10 the reverse sweeps and phase 11 the reverse
  * gravity map of vp_grad and vp_*_adjoint, phase 12 a pass of two velocity
  * sweeps over half velocity blocks or plane slices (blocks too large for one
- * pass). Arrays
- * have VP_NPHASE entries and are caller-owned host memory. */
-#define VP_NPHASE 13
+ * pass), phase 13 the one-pass reverse half kick (vp_kick_adjoint, vp_grad).
+ * Arrays have VP_NPHASE entries and are caller-owned host memory. */
+#define VP_NPHASE 14
 int vp_profile_enable(vp_ctx* ctx, int32_t on);
 int vp_profile_read(vp_ctx* ctx, double ms_out[VP_NPHASE], int64_t count_out[VP_NPHASE]);
 

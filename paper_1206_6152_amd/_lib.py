@@ -36,9 +36,9 @@ EXPORTS = ["vp_config_size", "vp_config_validate", "vp_init", "vp_step", "vp_run
            "vp_grad", "vp_stream_copy", "vp_cell_self_integral", "vp_sweep_adjoint_noalloc", "vp_free",
            "vp_last_error"]
 VP_NOALLOC_MAX_LINES = 4194304
-VP_NPHASE = 13
+VP_NPHASE = 14
 PHASES = ["x", "y", "z", "vx", "vy", "vz", "gravity", "kick", "kick2", "drift_yz", "adjoint_sweep",
-          "adjoint_gravity", "kick_pair"]
+          "adjoint_gravity", "kick_pair", "adjoint_kick"]
 
 
 class VPError(RuntimeError):

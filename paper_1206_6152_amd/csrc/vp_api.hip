@@ -463,7 +463,7 @@ int kick_adjoint(vp_ctx* c, double tau, const void* fin, void* lam, double* lam_
     a.lam_a[l] = lam_a ? lam_a + (long long)l * c->np : nullptr;
   }
   const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
-  PhaseScope scope(c, 10);
+  PhaseScope scope(c, 13);
   LAUNCH(c, vp::launch_kick_adjoint(a, c->cfg.dtype, nv, c->stream));
   return VP_OK;
 }
