@@ -575,15 +575,20 @@ hipError_t launch_kick_planes(const KickArgs& a, int dtype, const int nv[3], hip
 
 // 48^3 and 64^3 FP32 blocks: vz-slices of 16 planes (48^3; 147 KiB) or the
 // two-lines-per-lane pass on 16-cell vz-slices (64^3; 130 KiB), vy-slices of
-// 16 and 8 rows, vx-slices of 12 and 8 planes (150, 110 KiB; 130, 130 KiB)
+// 16 and 8 rows, vx-slices of 12 and 8 planes (150, 110 KiB; 130, 130 KiB).
+// 48^3 FP64 blocks: slices of 8 planes or rows for all three passes (64-byte
+// vz runs, 147 KiB each). FP64 64^3 would leave 32-byte vz runs and keeps the
+// four-pass route.
 bool kick_slices_supported(int dtype, const int nv[3])
 {
-  return dtype == 0 && nv[0] == nv[1] && nv[1] == nv[2] && (nv[0] == 48 || nv[0] == 64);
+  if (nv[0] != nv[1] || nv[1] != nv[2]) return false;
+  return dtype == 0 ? (nv[0] == 48 || nv[0] == 64) : nv[0] == 48;
 }
 
 hipError_t launch_kick_slices(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)
 {
   if (!kick_slices_supported(dtype, nv) || pass < 0 || pass > 2) return hipErrorInvalidValue;
+  if (dtype == 1) return launch_kick_slices<double, 48, 8, 8, 8>(a, pass, s);
   return nv[0] == 48 ? launch_kick_slices<float, 48, 16, 16, 12>(a, pass, s)
                      : launch_kick_slices<float, 64, 8, 8, 8>(a, pass, s);
 }
