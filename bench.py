@@ -179,10 +179,10 @@ def x_sweep_sums(w, elem_bytes):
 def kernel_name(phase, w, elem_bytes):
     t = "float" if elem_bytes == 4 else "double"
     if phase in ("kick", "kick2"):
+        if elem_bytes == 8 and tuple(w.nv) == (32, 32, 32):
+            return "vp::kick_lines_f64<%d>" % (2 if phase == "kick2" else 1)
         return "vp::kick_block<%s, %d, %d, %d, %d>" % (t, w.nv[0], w.nv[1], w.nv[2], 2 if phase == "kick2" else 1)
     if phase == "kick_pair":
-        if elem_bytes == 8 and w.nv[0] == 32:
-            return "vp::kick_pair_block<double, 32, 0, 8>"   # first of the three quarter-block passes
         return "vp::kick_pair_block<%s, %d, 2, %d>" % (t, w.nv[0], plane_slices(w, elem_bytes))
     if phase == "drift_yz":
         # (velocity cells per chunk, tiles per workgroup, chunks per cache line)
@@ -264,8 +264,10 @@ def gpu_run(w, vp_dtype, steps, warmup):
         tops = ops / (dom_ms * 1e-3) / 1e12
         valu = dict(achieved=tops, derived_peak=PEAK_VALU_TOPS, unit="T lane-ops/s",
                     fraction_of_derived_peak=tops / PEAK_VALU_TOPS, algorithmic_ops_per_launch=ops,
-                    peak_derivation="256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, unpacked FP32 issue "
-                                    "(published 157.3 TFLOP/s / 2 for FMA / 2 for packed pairs)")
+                    peak_derivation=("256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, unpacked FP32 issue "
+                                     "(published 157.3 TFLOP/s / 2 for FMA / 2 for packed pairs)" if s == 4 else
+                                     "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, FP64 issue "
+                                     "(published 78.6 TFLOP/s / 2 for FMA)"))
     return dict(
         value=cells * steps / wall,
         ms_per_step=step_ms,

@@ -118,12 +118,12 @@ int vp_sweep(vp_ctx* ctx, int32_t axis, double tau);
  * exactly the corresponding vp_sweep calls in that order (same arithmetic, same
  * result bit for bit); vp_kick runs the three velocity sweeps of a spatial
  * cell in one pass over f when that cell's velocity block fits on chip
- * (cubic velocity grids, FP32 up to 32^3, FP64 up to 24^3; FP64 32^3 in two
- * passes over half blocks, T_vx T_vy then T_vz; 48^3 and 64^3 as a T_vx
- * sweep then T_vy T_vz in one pass over slices of whole (vy, vz) planes),
- * and vp_drift runs
- * T_z and T_y in one pass when a (y, z) plane of a slab of velocity cells
- * fits on chip (square 16^2, 24^2 or 32^2 planes), then T_x. */
+ * (cubic velocity grids: FP32 up to 32^3 and FP64 up to 24^3 in LDS, FP64
+ * 32^3 in registers with one line per lane; 48^3 and 64^3 as a T_vx sweep
+ * then T_vy T_vz in one pass over slices of whole (vy, vz) planes), and
+ * vp_drift runs T_z and T_y in one pass when a (y, z) plane of a chunk of
+ * velocity cells fits on chip (square planes of 16, 24, 32 or 48 cells, and
+ * 64 in FP32), then T_x. */
 int vp_kick(vp_ctx* ctx, double tau);
 int vp_drift(vp_ctx* ctx, double tau);
 
@@ -176,7 +176,7 @@ int vp_dt(vp_ctx* ctx, double cfl, double* dt_host);
  * kick, phase 8 the one-pass pair of half kicks of vp_run, phase 9 the
  * one-pass T_y T_z, phase 10 the reverse sweeps and phase 11 the reverse
  * gravity map of vp_grad and vp_*_adjoint, phase 12 a pass of two velocity
- * sweeps over half velocity blocks or plane slices (blocks too large for one
+ * sweeps over slices of 48^3 or 64^3 velocity blocks (too large for one
  * pass), phase 13 the one-pass reverse half kick (vp_kick_adjoint, vp_grad).
  * Arrays have VP_NPHASE entries and are caller-owned host memory. */
 #define VP_NPHASE 14

@@ -537,6 +537,155 @@ hipError_t launch_kick_planes(const KickArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
+
+// ---- FP64 32^3 blocks: the sweeps of one or two half kicks in one pass ------
+// A block of 32^3 doubles (256 KiB) does not fit in LDS, so here it lives in
+// registers: each of the 1024 lanes holds one whole line of the block along
+// the axis being swept. Between sweeps along different axes the block changes
+// hands through LDS in two halves: the lines of one orientation (S) are
+// written and those of the next (D) read back. S and D lines share one
+// coordinate (the third axis), and each lane holds its S line and its D line
+// in the same half of it (both lane maps put that coordinate's top bit on the
+// same lane bit), so a lane writes its old line before it reads its new one
+// and never holds two. Half 0 trades first; half 1 writes while half 0 sweeps
+// its new lines, and lines left unswept by half 1 are swept while half 0 of
+// the next exchange writes, so LDS traffic overlaps the arithmetic. Every axis
+// is held in its sweep's orientation (reversed where nu < 0), as in
+// kick_block, and each sweep's whole-cell shift is applied where its lines
+// are written to LDS. LDS layouts, in doubles of oriented (x, y, z):
+//   x <-> y (halves of z):  528 x + 16 y + (z & 15)
+//   y <-> z (halves of x):  1072 (x & 15) + 33 y + z
+//   z <-> x (halves of y):  512 x + 32 (y & 15) + (z ^ g),
+//                           g = 16 (y & 1) + 2 ((y & 15) >> 1) + (x & 1),
+// so that 32 consecutive lanes touch 32 different bank pairs in every access.
+// Lane maps (lane t, t[i:j] its bits i..j):
+//   x lines (y, z): z = t[0:3] + 16 t[9], y = t[4:7] + 16 t[8]
+//   y lines (x, z): z = t[0:3] + 16 t[9], x = t[4:6] + 8 t[8] + 16 t[7]
+//   z lines (x, y): y = t[0:3] + 16 t[8], x = t[4:6] + 8 t[9] + 16 t[7]
+// The first x lines come straight from HBM and the last ones go straight back
+// (each row of a wave is four runs of 16 values); after the last z sweep one
+// more exchange hands the block to x lines for that.
+constexpr int KL_N = 32;
+constexpr int KL_ELEMS = 1072 * 15 + 33 * 31 + 31 + 1;   // the largest layout's extent
+
+template <int REPS>
+__global__ __launch_bounds__(1024) void kick_lines_f64(KickArgs a)
+{
+  constexpr int N = KL_N;
+  constexpr unsigned ROWB = N * N * 8u;                   // bytes between vx planes
+  constexpr unsigned BLKB = N * N * N * 8u;
+  __shared__ double L[KL_ELEMS];
+  const int t = threadIdx.x;
+  const long long s = blockIdx.x;
+  const auto rs = buf_rsrc(static_cast<const double*>(a.f) + s * (N * N * N), BLKB);
+  const auto ws = a.out ? buf_rsrc(static_cast<const double*>(a.out) + s * (N * N * N), BLKB) : rs;
+  const KickTab<double>* __restrict__ tab = static_cast<const KickTab<double>*>(a.tab) + s;
+  const bool rx = tab_neg(tab->neg, 0), ry = tab_neg(tab->neg, 1), rz = tab_neg(tab->neg, 2);
+  const double ax = tab->alpha[0], ay = tab->alpha[1], az = tab->alpha[2];
+  const double c1x = tab->c1[0], c1y = tab->c1[1], c1z = tab->c1[2];
+  const double c2x = tab->c2[0], c2y = tab->c2[1], c2z = tab->c2[2];
+  const int shx = tab->shift[0], shy = tab->shift[1], shz = tab->shift[2];
+  const int b7 = (t >> 7) & 1, b8 = (t >> 8) & 1, b9 = (t >> 9) & 1;
+  const int lo = t & 15;
+  const int xl_z = lo + 16 * b9, xl_y = ((t >> 4) & 15) + 16 * b8;            // x line (y, z)
+  const int yl_z = lo + 16 * b9, yl_x = ((t >> 4) & 7) + 8 * b8 + 16 * b7;    // y line (x, z)
+  const int zl_y = lo + 16 * b8, zl_x = ((t >> 4) & 7) + 8 * b9 + 16 * b7;    // z line (x, y)
+  double v[N];
+
+  auto sweep_x = [&]() { pfc_core<double, N>(v, ax, c1x, c2x, false); };
+  auto sweep_y = [&]() { pfc_core<double, N>(v, ay, c1y, c2y, false); };
+  auto sweep_z = [&]() { pfc_core<double, N>(v, az, c1z, c2z, false); };
+  auto write_x = [&]() {
+    const int base = xl_y * 16 + (xl_z & 15);
+    store_shifted<double, N>(v, shx, false, [&](int d, double x) { L[base + d * 528] = x; });
+  };
+  auto read_y = [&]() {
+    const int base = yl_x * 528 + (yl_z & 15);
+#pragma unroll
+    for (int r = 0; r < N; r++) v[r] = L[base + r * 16];
+  };
+  auto write_y = [&]() {
+    const int base = (yl_x & 15) * 1072 + yl_z;
+    store_shifted<double, N>(v, shy, false, [&](int d, double x) { L[base + d * 33] = x; });
+  };
+  auto read_z = [&]() {
+    const int base = (zl_x & 15) * 1072 + zl_y * 33;
+#pragma unroll
+    for (int r = 0; r < N; r++) v[r] = L[base + r];
+  };
+  auto write_z = [&]() {
+    const int yl = zl_y & 15;
+    const int base = zl_x * 512 + yl * 32;
+    const int g = 16 * (yl & 1) + 2 * (yl >> 1) + (zl_x & 1);
+    store_shifted<double, N>(v, shz, false, [&](int d, double x) { L[base + (d ^ g)] = x; });
+  };
+  auto read_x = [&]() {
+    const int yl = xl_y & 15;
+    const int zg = xl_z ^ (16 * (yl & 1) + 2 * (yl >> 1));   // z ^ g without the x bit
+    const int base = yl * 32;
+#pragma unroll
+    for (int r = 0; r < N; r++) v[r] = L[r * 512 + base + (zg ^ (r & 1))];
+  };
+  // one change of orientation, halves by lane bit h; pend: the S line still
+  // awaits its sweep
+  auto exchange = [&](bool h, bool pend, auto&& sweepS, auto&& writeS, auto&& readD, auto&& sweepD) {
+    if (pend) sweepS();
+    if (!h) writeS();
+    __syncthreads();
+    if (!h) readD();
+    __syncthreads();
+    if (!h) sweepD();
+    else writeS();
+    __syncthreads();
+    if (h) readD();
+    __syncthreads();
+  };
+
+  // x lines from HBM: lane (y, z) reads rows x in its sweep orientation
+  const int ys = ry ? N - 1 - xl_y : xl_y, zs = rz ? N - 1 - xl_z : xl_z;
+  const unsigned voff = (unsigned)(ys * N + zs) * 8u;
+#pragma unroll
+  for (int r = 0; r < N; r++) v[r] = buf_load<double>(rs, voff, (unsigned)(rx ? N - 1 - r : r) * ROWB);
+  exchange(b9, true, sweep_x, write_x, read_y, sweep_y);
+  exchange(b7, b9, sweep_y, write_y, read_z, sweep_z);
+  if constexpr (REPS == 2) {
+    exchange(b8, b7, sweep_z, write_z, read_x, sweep_x);
+    exchange(b9, b8, sweep_x, write_x, read_y, sweep_y);
+    exchange(b7, b9, sweep_y, write_y, read_z, sweep_z);
+  }
+  // the last z lines go to x lines, which go back to HBM as they arrive
+  auto store_x = [&]() {
+#pragma unroll
+    for (int r = 0; r < N; r++) buf_store<double>(ws, voff, (unsigned)(rx ? N - 1 - r : r) * ROWB, v[r]);
+  };
+  const bool pend = b7, h = b8;
+  if (pend) sweep_z();
+  if (!h) write_z();
+  __syncthreads();
+  if (!h) read_x();
+  __syncthreads();
+  if (!h) store_x();
+  else write_z();
+  __syncthreads();
+  if (h) {
+    read_x();
+    store_x();
+  }
+}
+
+hipError_t launch_kick_lines_f64(const KickArgs& a, hipStream_t s)
+{
+  static_assert(KL_ELEMS * 8 <= 160 * 1024, "LDS");
+  if (a.np <= 0) return hipSuccess;
+  const hipError_t e = launch_kick_table<double, KL_N>(a, s);
+  if (e != hipSuccess) return e;
+  if (a.reps == 2)
+    hipLaunchKernelGGL((kick_lines_f64<2>), dim3((unsigned)a.np), dim3(1024), 0, s, a);
+  else
+    hipLaunchKernelGGL((kick_lines_f64<1>), dim3((unsigned)a.np), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Velocity cubes whose block fits the LDS of one workgroup: FP32 up to 32^3,
@@ -554,9 +703,15 @@ size_t kick_table_bytes(int dtype, long long np)
   return (size_t)np * (dtype == 0 ? sizeof(KickTab<float>) : sizeof(KickTab<double>));
 }
 
-bool kick_pair_supported(int dtype, const int nv[3])
+bool kick_lines_supported(int dtype, const int nv[3])
 {
-  return dtype == 1 && nv[0] == 32 && nv[1] == 32 && nv[2] == 32;
+  return dtype == 1 && nv[0] == KL_N && nv[1] == KL_N && nv[2] == KL_N;
+}
+
+hipError_t launch_kick_lines(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)
+{
+  if (!kick_lines_supported(dtype, nv) || (a.reps != 1 && a.reps != 2)) return hipErrorInvalidValue;
+  return launch_kick_lines_f64(a, s);
 }
 
 // 48^3 and 64^3 blocks: slices of 12 and 8 planes in FP32 (110 and 130
@@ -591,15 +746,6 @@ hipError_t launch_kick_slices(const KickArgs& a, int dtype, const int nv[3], int
   if (dtype == 1) return launch_kick_slices<double, 48, 8, 8, 8>(a, pass, s);
   return nv[0] == 48 ? launch_kick_slices<float, 48, 16, 16, 12>(a, pass, s)
                      : launch_kick_slices<float, 64, 8, 8, 8>(a, pass, s);
-}
-
-// FP64 32^3 blocks: quarter-block slices (8 planes or rows, 66 KiB), two
-// workgroups per CU, the vz-slices grouped per XCD (3.05 ms per pass on the
-// 32^3 x 32^3 grid, against 3.25 for half blocks with one workgroup per CU)
-hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s)
-{
-  if (!kick_pair_supported(dtype, nv) || pass < 0 || pass > 2) return hipErrorInvalidValue;
-  return launch_kick_slices<double, 32, 8, 8, 8>(a, pass, s);
 }
 
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s)

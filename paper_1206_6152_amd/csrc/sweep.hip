@@ -30,9 +30,9 @@
 // segment. Contiguous lines (the vz axis) are staged through LDS so that the
 // HBM traffic stays coalesced, then transposed into registers. Several sweeps
 // share one pass over HBM where their lines fit on chip together: a half kick
-// (or two in a row) on a whole velocity block, two velocity sweeps on half a
-// block or on slices of whole (vy, vz) planes, and T_z T_y on an x index times
-// a chunk of velocity cells. The alpha, c1, c2 of a line are computed in FP64
+// (or two in a row) on a whole velocity block, in LDS or, for FP64 32^3
+// blocks, in registers with LDS between axes; two velocity sweeps on slices
+// of a block; and T_z T_y on an x index times a chunk of velocity cells. The alpha, c1, c2 of a line are computed in FP64
 // and rounded once to the storage type. The whole-cell part m of the shift is
 // applied as the line is written out: each cell goes once to its shifted place.
 #include "vp_internal.h"

@@ -525,33 +525,21 @@ int kick_n(vp_ctx* c, double tau, int reps)
     LAUNCH(c, vp::launch_kick(a, c->cfg.dtype, nv, c->stream));
     return VP_OK;
   }
-  int r;
-  if (vp::kick_pair_supported(c->cfg.dtype, nv)) {
+  if (vp::kick_lines_supported(c->cfg.dtype, nv)) {   // FP64 32^3: one line per lane, LDS between axes
     vp::KickArgs a{};
     a.tab = c->ktab;
     a.f = c->f;
     a.np = c->np;
-    a.reps = 1;
+    a.reps = reps;
     for (int l = 0; l < 3; l++) {
       a.a[l] = c->accel + (long long)l * c->np;
       a.scale[l] = tau / c->dv[l];
     }
-    if (reps == 2) {   // T_vx T_vy | T_vz T_vx | T_vy T_vz
-      for (int pass = 0; pass < 3; pass++) {
-        PhaseScope scope(c, 12);
-        LAUNCH(c, vp::launch_kick_pair(a, c->cfg.dtype, nv, pass, c->stream));
-      }
-      return VP_OK;
-    }
-    for (int i = 0; i < reps; i++) {
-      {
-        PhaseScope scope(c, 12);
-        LAUNCH(c, vp::launch_kick_pair(a, c->cfg.dtype, nv, 0, c->stream));
-      }
-      if ((r = sweep(c, 5, tau))) return r;
-    }
+    PhaseScope scope(c, reps == 2 ? 8 : 7);
+    LAUNCH(c, vp::launch_kick_lines(a, c->cfg.dtype, nv, c->stream));
     return VP_OK;
   }
+  int r;
   if (vp::kick_planes_supported(c->cfg.dtype, nv)) {   // T_vx | T_vy T_vz per half kick
     vp::KickArgs a{};
     a.tab = c->ktab;
@@ -742,7 +730,7 @@ int vp_init(const vp_config* cfg, void* f_dev, void* hip_stream, vp_ctx** out)
   }
   {
     const int nv[3] = {cfg->nv[0], cfg->nv[1], cfg->nv[2]};
-    if ((vp::kick_fused_supported(cfg->dtype, nv) || vp::kick_pair_supported(cfg->dtype, nv) ||
+    if ((vp::kick_fused_supported(cfg->dtype, nv) || vp::kick_lines_supported(cfg->dtype, nv) ||
          vp::kick_planes_supported(cfg->dtype, nv)) &&
         (r = dalloc(&c->ktab, vp::kick_table_bytes(cfg->dtype, c->np), "kick coefficients"))) {
       release(c);

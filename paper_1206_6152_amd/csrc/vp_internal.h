@@ -71,19 +71,18 @@ size_t kick_table_bytes(int dtype, long long np);
 bool kick_fused_supported(int dtype, const int nv[3]);
 hipError_t launch_kick(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
 
-// Two consecutive velocity sweeps in one pass over slices of FP64 32^3
-// velocity blocks (the whole block does not fit on chip): pass 0 = T_vy T_vx
-// on vz-slices, pass 1 = T_vx T_vz on vy-slices, pass 2 = T_vz T_vy on
-// vx-slices (rightmost first), each slice a quarter block. A half kick is
-// pass 0 and a T_vz sweep; two half kicks in a row are passes 0, 1, 2. Pass 0
-// also fills the coefficient table.
-bool kick_pair_supported(int dtype, const int nv[3]);
+// FP64 32^3 blocks: one half kick (reps 1) or two with the same acceleration
+// (reps 2) in one pass, the block held in registers (one line per lane) and
+// changing orientation through LDS in halves.
+bool kick_lines_supported(int dtype, const int nv[3]);
+hipError_t launch_kick_lines(const KickArgs& a, int dtype, const int nv[3], hipStream_t s);
+
 // The six sweeps of two consecutive half kicks in three passes over slices
 // (T_vx T_vy on vz-slices, T_vz T_vx on vy-slices, T_vy T_vz on vx-slices),
-// for FP32 48^3 and 64^3 blocks; pass 0 also fills the coefficient table.
+// for FP32 48^3 and 64^3 and FP64 48^3 blocks; pass 0 also fills the
+// coefficient table.
 bool kick_slices_supported(int dtype, const int nv[3]);
 hipError_t launch_kick_slices(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
-hipError_t launch_kick_pair(const KickArgs& a, int dtype, const int nv[3], int pass, hipStream_t s);
 // T_vy then T_vz in one pass over slices of whole (vy, vz) planes, for
 // velocity blocks too large for the passes above (48^3 and 64^3: 12 and 8
 // planes in FP32, 6 and 4 in FP64, 110 and 130 KiB per slice). A half kick is
