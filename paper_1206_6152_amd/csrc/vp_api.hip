@@ -1030,12 +1030,13 @@ int copy_f(vp_ctx* c, void* dst, const void* src, size_t bytes)
 }
 
 // dst = T_vz T_vy T_vx(tau) src (dst may not alias src): one pass when the
-// velocity block fits on chip, else a copy and the kick in place. c->f is
-// left pointing at dst.
+// velocity block fits on chip (in LDS, or in registers for FP64 32^3), else a
+// copy and the kick in place. c->f is left pointing at dst.
 int kick_to(vp_ctx* c, double tau, const void* src, void* dst, size_t fbytes)
 {
   const int nv[3] = {c->cfg.nv[0], c->cfg.nv[1], c->cfg.nv[2]};
-  if (vp::kick_fused_supported(c->cfg.dtype, nv)) {
+  const bool lines = vp::kick_lines_supported(c->cfg.dtype, nv);
+  if (lines || vp::kick_fused_supported(c->cfg.dtype, nv)) {
     vp::KickArgs a{};
     a.tab = c->ktab;
     a.f = const_cast<void*>(src);
@@ -1048,7 +1049,8 @@ int kick_to(vp_ctx* c, double tau, const void* src, void* dst, size_t fbytes)
     }
     c->f = dst;
     PhaseScope scope(c, 7);
-    LAUNCH(c, vp::launch_kick(a, c->cfg.dtype, nv, c->stream));
+    LAUNCH(c, lines ? vp::launch_kick_lines(a, c->cfg.dtype, nv, c->stream)
+                    : vp::launch_kick(a, c->cfg.dtype, nv, c->stream));
     return VP_OK;
   }
   int r = copy_f(c, dst, src, fbytes);

@@ -278,6 +278,37 @@ def test_adjoint_workload_grid_gradient_matches_oracle():
             assert err <= 2e-3
 
 
+def test_grad_fp64_register_kick_blocks_match_oracle():
+    # FP64 32^3 velocity blocks take the one-pass kick that holds the block in
+    # registers, also where a segment's recomputed first half kick is written
+    # straight into the next state's buffer; the gradient must match the
+    # oracle's and be the same bits for every checkpoint interval
+    s = inputs.jeans_sigma(0.5, 2 * np.pi)
+    w = inputs.Workload(name="t", n=(2, 2, 2), nv=(32, 32, 32), L=(0.5, 0.5, 0.5), vmin=(-4 * s,) * 3,
+                        vmax=(4 * s,) * 3, G=1.0, bc=0, dt=0.04, steps=3, params=dict(sigma=s, amp=0.1))
+    f0 = inputs.initial_f(w)
+    f0 *= 1 + 0.05 * np.random.default_rng(5).standard_normal(w.n).reshape(w.n + (1, 1, 1))
+    f0 = f0 * (1 + 1e-4 * np.random.default_rng(12).uniform(0, 1, f0.shape))
+    L_ref, g_ref = oracle.grad(oracle_grid(w), f0, w.steps, w.dt)
+    outs = []
+    for ckpt in (1, 2, 8):
+        f = _dev(f0, np.float64)
+        sim = Simulator(config_of(w, VP_F64), f)
+        sim.profile(True)
+        L, g = sim.grad(w.steps, w.dt, ckpt)
+        phases = sim.profile_read()
+        outs.append((L, g.cpu().numpy(), f.cpu().numpy()))
+        sim.close()
+        assert phases["kick"][1] + phases["kick2"][1] > 0 and phases["vz"][1] == 0
+    print("grad FP64 32^3 blocks: L", outs[0][0], L_ref, "rel L1", rel_l1(outs[0][1], g_ref), flush=True)
+    assert outs[0][0] == pytest.approx(L_ref, rel=1e-12)
+    assert rel_l1(outs[0][1], g_ref) <= 1e-10
+    for L, g, fin in outs[1:]:
+        assert L == outs[0][0]
+        assert np.array_equal(g, outs[0][1])
+        assert np.array_equal(fin, outs[0][2])
+
+
 @pytest.mark.parametrize("dtype", [VP_F64, VP_F32])
 @pytest.mark.parametrize("bc", [VP_BC_PERIODIC, VP_BC_ISOLATED])
 def test_grad_same_bits_for_every_checkpoint_interval(bc, dtype):
