@@ -60,6 +60,48 @@ def test_kick_equals_three_sweeps_and_oracle(dtype, nv, nu_max):
     assert rel_l1(fused, ref) <= tol
 
 
+@pytest.mark.parametrize("dtype,nv", [(VP_F32, 32), (VP_F64, 24), (VP_F64, 32), (VP_F32, 48), (VP_F64, 48)])
+@pytest.mark.parametrize("reps", [1, 2])
+def test_kick_degenerate_accelerations(dtype, nv, reps):
+    # spatial cells with no acceleration (nu = 0 on every axis), with nu at or
+    # next to a whole number of cells (alpha near 0), with |nu| beyond the
+    # block (everything leaves through the outflow boundary), and mixes of
+    # these over the three axes; one or two vp_kick calls must equal the
+    # single sweeps bit for bit
+    print("case", dtype, nv, reps, flush=True)
+    w = small_workload(VP_BC_PERIODIC, n=(2, 2, 2), nv=(nv, nv, nv))
+    f0 = structured_f(w.shape, seed=nv + 3).astype(NP[dtype]).astype(np.float64)
+    tau = 0.5
+    dv = np.array([w.dv(l) for l in range(3)])
+    nus = np.array([[0.0, 0.0, 0.0], [1.0, -2.0, 3.0], [nv + 5.5, -(nv + 0.25), 2.0 * nv],
+                    [0.0, -(nv + 1.0), 0.6], [-1.3, 0.0, 0.0], [0.25, 0.5, -0.75], [-7.0, 7.5, -0.0],
+                    [nv - 1.0, -(nv - 0.5), nv]])
+    a = np.zeros((3,) + w.n)
+    for c in range(8):
+        ix, iy, iz = c >> 2, (c >> 1) & 1, c & 1
+        a[:, ix, iy, iz] = nus[c] * dv / tau
+    outs = []
+    for mode in ("kick", "split"):
+        sim, f = _sim(w, f0, dtype, a)
+        for _ in range(reps):
+            if mode == "kick":
+                sim.kick(tau)
+            else:
+                for ax in (3, 4, 5):
+                    sim.sweep(ax, tau)
+        outs.append(f.cpu().numpy())
+        sim.close()
+    assert np.array_equal(outs[0], outs[1])
+    g = oracle_grid(w)
+    ref = f0
+    for _ in range(reps):
+        for ax in (3, 4, 5):
+            ref = oracle.sweep(g, ref, ax, tau, a)
+    assert rel_l1(outs[0], ref) <= (1e-14 if dtype == VP_F64 else 2e-6)
+    # cells whose nu passes the block on some axis are empty afterwards
+    assert not outs[0][0, 1, 0].any()
+
+
 @pytest.mark.parametrize("dtype", [VP_F32, VP_F64])
 def test_kick_non_cubic_velocity_grid_falls_back(dtype):
     w = small_workload(VP_BC_PERIODIC, n=(2, 2, 3), nv=(8, 12, 16))
