@@ -361,13 +361,37 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
     const int jz = e % N, jy = (e / N) % N, jx = e / (N * N);
     return jx * S::SX + jy * S::SY + jz;
   };
-  auto stage = [&](T* dst, const T* src) {
-    for (int k = tid; k < NVEC; k += S::THREADS) {
-      const VT x = reinterpret_cast<const VT*>(src)[k];
-      const int b = place(k * V);
+  // staging: every 16-byte load of a lane is in flight before its first LDS
+  // write (a rolled loop would wait out one load latency per vector); the
+  // opaque copies of the lane index keep the compiler from holding the
+  // addresses of every staging for the whole kernel
+  constexpr int PER = (NVEC + S::THREADS - 1) / S::THREADS;
+  auto load = [&](VT (&x)[PER], const T* src) {
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
 #pragma unroll
-      for (int q = 0; q < V; q++) dst[b + q] = lane_of<VT, T>(x, q);
+    for (int j = 0; j < PER; j++) {
+      const int k = t0 + j * S::THREADS;
+      if (k < NVEC) x[j] = reinterpret_cast<const VT*>(src)[k];
     }
+  };
+  auto park = [&](T* dst, const VT (&x)[PER]) {
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      const int k = t0 + j * S::THREADS;
+      if (k < NVEC) {
+        const int b = place(k * V);
+#pragma unroll
+        for (int q = 0; q < V; q++) dst[b + q] = lane_of<VT, T>(x[j], q);
+      }
+    }
+  };
+  auto stage = [&](T* dst, const T* src) {
+    VT x[PER];
+    load(x, src);
+    park(dst, x);
   };
   // forward sweep of B along vx (lanes (jy, jz)) or vy (lanes (jx, jz)), in place
   auto forward = [&](int axis, double nu) {
@@ -395,8 +419,13 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
     }
     __syncthreads();
   };
-  stage(B, xg);
-  stage(C, lg);
+  {
+    VT x[PER], l[PER];
+    load(x, xg);
+    load(l, lg);
+    park(B, x);
+    park(C, l);
+  }
   __syncthreads();
   forward(0, nux);
   forward(1, nuy);
@@ -408,13 +437,17 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
   stage(B, xg);
   __syncthreads();
   reverse(0, nux);
-  for (int k = tid; k < NVEC; k += S::THREADS) {
-    const int b = place(k * V);
-    VT x;
-    T* xs = reinterpret_cast<T*>(&x);
 #pragma unroll
-    for (int q = 0; q < V; q++) xs[q] = C[b + q];
-    reinterpret_cast<VT*>(lg)[k] = x;
+  for (int j = 0; j < PER; j++) {
+    const int k = tid + j * S::THREADS;
+    if (k < NVEC) {
+      const int b = place(k * V);
+      VT x;
+      T* xs = reinterpret_cast<T*>(&x);
+#pragma unroll
+      for (int q = 0; q < V; q++) xs[q] = C[b + q];
+      reinterpret_cast<VT*>(lg)[k] = x;
+    }
   }
   // lam_a[l][s] += scale_l * sum of the block's line adjoints, in the order of
   // reduce_lines_kernel: lane t < 256 adds lines t, t + 256, ..., then a tree
