@@ -38,18 +38,38 @@ namespace {
 // order then writes out_{i-1} once cell i is known: cell i sends its own terms
 // to out_i, its Lp interior-branch term to out_{i+1} and its Lm interior-branch
 // term to out_{i-1}.
-// la(r, x) gives the lam value of cell r from its stored value x
-template <typename T, int N, typename AT, typename LA>
+// la(r, x) gives the lam value of cell r from its stored value x.
+// GATHER (lines in LDS): lam_g is read straight into view order, each view
+// cell from the storage cell that the mirror and the transposed shift name,
+// instead of loading lam in storage order and permuting registers with
+// selects (N^2 of them for the shift); the same values land in the same
+// registers.
+template <typename T, int N, bool GATHER = false, typename AT, typename LA>
 __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at, LA la)
 {
 #pragma clang fp contract(off)
   const LineCoef<T> k = line_coef<T, N>(nu, periodic);
   const bool neg = k.neg;
   T w[N], l[N];
+  if constexpr (GATHER) {
+    const int m = neg ? -k.shift : k.shift;   // >= 0, below N when periodic
 #pragma unroll
-  for (int r = 0; r < N; r++) {
-    w[r] = fin[at(r)];
-    l[r] = la(r, lam[at(r)]);
+    for (int r = 0; r < N; r++) w[r] = fin[at(r)];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      int j = i + m;
+      if (periodic && j >= N) j -= N;
+      const bool in = j < N;                  // else past an outflow end: zero
+      const int rs = in ? (neg ? N - 1 - j : j) : 0;
+      const T x = la(rs, lam[at(rs)]);
+      l[i] = in ? x : T(0);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < N; r++) {
+      w[r] = fin[at(r)];
+      l[r] = la(r, lam[at(r)]);
+    }
   }
   // f_inf and the first storage cell that holds it
   T finf = T(0);
@@ -66,12 +86,14 @@ __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool
     const T x = w[i], y = w[N - 1 - i];
     w[i] = neg ? y : x;
     w[N - 1 - i] = neg ? x : y;
-    const T p = l[i], q = l[N - 1 - i];
-    l[i] = neg ? q : p;
-    l[N - 1 - i] = neg ? p : q;
+    if constexpr (!GATHER) {
+      const T p = l[i], q = l[N - 1 - i];
+      l[i] = neg ? q : p;
+      l[N - 1 - i] = neg ? p : q;
+    }
   }
   const int m = neg ? -k.shift : k.shift;
-  if (m != 0) {
+  if (!GATHER && m != 0) {
     T g[N];
 #pragma unroll
     for (int i = 0; i < N; i++) {
@@ -166,10 +188,10 @@ __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool
   return neg ? -(double)lalpha : (double)lalpha;
 }
 
-template <typename T, int N, typename AT>
+template <typename T, int N, bool GATHER = false, typename AT>
 __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at)
 {
-  return adj_line<T, N>(fin, lam, nu, periodic, at, [](int, T x) { return x; });
+  return adj_line<T, N, GATHER>(fin, lam, nu, periodic, at, [](int, T x) { return x; });
 }
 
 __device__ __forceinline__ double adj_line_nu(const SweepArgs& a, long long o, long long c)
@@ -394,7 +416,10 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
     park(dst, x);
   };
   // forward sweep of B along vx (lanes (jy, jz)) or vy (lanes (jx, jz)), in place
-  auto forward = [&](int axis, double nu) {
+  // the sweep lambdas are inlined at each call, so that their axis, hence
+  // every LDS stride, is a constant there (a shared out-of-line body takes the
+  // strides at run time and spills across the calls)
+  auto forward = [&](int axis, double nu) __attribute__((always_inline)) {
     if (tid < S::LINES) {
       const int o = tid / N, i = tid - o * N;
       const int base = axis == 0 ? o * S::SY + i : o * S::SX + i;
@@ -408,14 +433,14 @@ __global__ __launch_bounds__((AdjKickShape<T, N>::THREADS)) void kick_adj_block(
     __syncthreads();
   };
   // reverse sweep along `axis` at forward input B, lam in C, in place
-  auto reverse = [&](int axis, double nu) {
+  auto reverse = [&](int axis, double nu) __attribute__((always_inline)) {
     if (tid < S::LINES) {
       const int o = tid / N, i = tid - o * N;
       int base, st;
       if (axis == 2) { base = o * S::SX + i * S::SY; st = 1; }          // vz lines, lanes (jx, jy)
       else if (axis == 1) { base = o * S::SX + i; st = S::SY; }        // vy lines, lanes (jx, jz)
       else { base = o * S::SY + i; st = S::SX; }                      // vx lines, lanes (jy, jz)
-      dn[axis][tid] = adj_line<T, N>(B, C, nu, false, [&](int r) { return base + r * st; });
+      dn[axis][tid] = adj_line<T, N, true>(B, C, nu, false, [&](int r) { return base + r * st; });
     }
     __syncthreads();
   };
