@@ -39,11 +39,11 @@ namespace {
 // to out_i, its Lp interior-branch term to out_{i+1} and its Lm interior-branch
 // term to out_{i-1}.
 // la(r, x) gives the lam value of cell r from its stored value x.
-// GATHER (lines in LDS): lam_g is read straight into view order, each view
-// cell from the storage cell that the mirror and the transposed shift name,
-// instead of loading lam in storage order and permuting registers with
-// selects (N^2 of them for the shift); the same values land in the same
-// registers.
+// GATHER (lines in LDS): where the line has a whole-cell shift, lam_g is
+// read straight into view order, each view cell from the storage cell that
+// the mirror and the transposed shift name, instead of loading lam in
+// storage order and permuting registers with selects (N^2 of them for the
+// shift); the same values land in the same registers.
 template <typename T, int N, bool GATHER = false, typename AT, typename LA>
 __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool periodic, AT at, LA la)
 {
@@ -55,14 +55,25 @@ __device__ __forceinline__ double adj_line(const T* fin, T* lam, double nu, bool
     const int m = neg ? -k.shift : k.shift;   // >= 0, below N when periodic
 #pragma unroll
     for (int r = 0; r < N; r++) w[r] = fin[at(r)];
+    if (m == 0) {                             // no shift: storage order, then the mirror
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-      int j = i + m;
-      if (periodic && j >= N) j -= N;
-      const bool in = j < N;                  // else past an outflow end: zero
-      const int rs = in ? (neg ? N - 1 - j : j) : 0;
-      const T x = la(rs, lam[at(rs)]);
-      l[i] = in ? x : T(0);
+      for (int r = 0; r < N; r++) l[r] = la(r, lam[at(r)]);
+#pragma unroll
+      for (int i = 0; i < N / 2; i++) {
+        const T p = l[i], q = l[N - 1 - i];
+        l[i] = neg ? q : p;
+        l[N - 1 - i] = neg ? p : q;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; i++) {
+        int j = i + m;
+        if (periodic && j >= N) j -= N;
+        const bool in = j < N;                // else past an outflow end: zero
+        const int rs = in ? (neg ? N - 1 - j : j) : 0;
+        const T x = la(rs, lam[at(rs)]);
+        l[i] = in ? x : T(0);
+      }
     }
   } else {
 #pragma unroll
