@@ -241,7 +241,7 @@ def gpu_run(w, vp_dtype, steps, warmup):
     hbm_gbps = sweep_bytes / (dom_ms * 1e-3) / 1e9
     step_ms = wall * 1e3 / steps
     step_bytes = 19.0 * s * cells          # 9 sweeps x 2 + one density read
-    # what a step of this build must move: every pass over f reads and writes it once
+    # what a step of these kernels must move: every pass over f reads and writes it once
     passes = sum(n for k, (ms, n) in phases.items()
                  if k not in ("gravity", "adjoint_sweep", "adjoint_gravity", "adjoint_kick")) / max(1, steps)
     fused_bytes = passes * 2.0 * s * cells
@@ -275,7 +275,7 @@ def gpu_run(w, vp_dtype, steps, warmup):
         dominant=dom,
         roofline=roof,
         valu=valu,
-        # bytes a step of this build moves (every pass reads and writes f once);
+        # bytes a step of these kernels moves (every pass reads and writes f once);
         # the unfused nine-sweep model is given as an equivalent rate only
         step_model=dict(passes_per_step=passes, fused_bytes_per_step=fused_bytes,
                         fused_GBps=fused_bytes / (step_ms * 1e-3) / 1e9,
@@ -382,8 +382,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the multi-GPU (x-slab) decomposition is a "
-              "design only in this build; use --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the multi-GPU (x-slab) decomposition is not "
+              "implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from paper_1206_6152_amd import VP_F32, VP_F64, inputs

@@ -48,7 +48,7 @@ extern "C" {
 #define VP_ENOMEM (-2)        /* device allocation failed */
 #define VP_EHIP (-3)          /* HIP runtime or kernel launch failure */
 #define VP_ENONFINITE (-4)    /* a diagnostic sum is not finite */
-#define VP_EUNSUPPORTED (-5)  /* valid request this build does not implement */
+#define VP_EUNSUPPORTED (-5)  /* valid request the library does not implement */
 
 #define VP_BC_PERIODIC 0
 #define VP_BC_ISOLATED 1
