@@ -463,7 +463,7 @@ def main():
     }
     if r64:
         out["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"],
-                       "step_model": r64["step_model"],
+                       "valu": r64["valu"], "step_model": r64["step_model"],
                        "phases_ms_per_launch": r64["phases_ms_per_launch"]}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
     print(json.dumps(out), flush=True)
