@@ -360,7 +360,54 @@ def cpu_baseline(w, seconds):
                 sample="FP64 oracle, %d steps of an 8^3-spatial x %s-velocity sub-grid of the same "
                        "workload (%.3g cells, same Courant numbers), %.1f s wall; host %s, %d logical CPUs"
                        % (steps, "x".join(map(str, sub.nv)), cells, el, platform.processor() or
-                          platform.machine(), os.cpu_count() or 0))
+                          platform.machine(), os.cpu_count() or 0),
+                cpu_model=cpu_model(), omp_num_threads=os.environ.get("OMP_NUM_THREADS"),
+                single_thread=cpu_baseline_one_thread(w, max(2.0, seconds / 2)))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+_ONE_THREAD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1206_6152_amd import inputs
+w = inputs.WORKLOADS[sys.argv[2]]()
+sub = inputs.Workload(name=w.name, n=(8, 8, 8), nv=w.nv, L=(0.25, 0.25, 0.25), vmin=w.vmin, vmax=w.vmax,
+                      G=w.G, bc=w.bc, dt=w.dt, steps=1, params=w.params)
+run = oracle.Run(oracle.Grid(n=sub.n, nv=sub.nv, L=sub.L, vmin=sub.vmin, vmax=sub.vmax, G=sub.G, bc=sub.bc),
+                 inputs.initial_f(sub))
+steps, t0 = 0, time.perf_counter()
+while True:
+    run.step(sub.dt)
+    steps += 1
+    el = time.perf_counter() - t0
+    if el >= float(sys.argv[3]) or steps >= 50:
+        break
+print(json.dumps(dict(value=sub.cells * steps / el, steps=steps, wall_s=el, threads=oracle.num_threads())))
+"""
+
+
+def cpu_baseline_one_thread(w, seconds):
+    """The same oracle sample on one host thread (OMP_NUM_THREADS=1 in a child
+    process, which touches no GPU)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT, w.name, str(seconds)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return dict(error=r.stderr.strip().splitlines()[-1] if r.stderr.strip() else "exit %d" % r.returncode)
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    out["unit"] = "cell-updates/s"
+    return out
 
 
 def main():
