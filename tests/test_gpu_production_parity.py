@@ -257,6 +257,36 @@ def test_benchmark_grid_two_steps_match_oracle():
     _whole_run(w, 2, contrast=w.params["amp"])
 
 
+def _slab_plane():
+    """One x cell of the slab workload with its whole 64 x 64 (y, z) plane and 64^3
+    velocity cells (1.07e9 cells): the same spacing, velocity grid, Maxwellian,
+    time step and density statistics, so the run takes the slab's own one-pass
+    kernels (64-cell (y, z) planes, 64^3 velocity slices)."""
+    w = inputs.slab_16_64_64x64()
+    return inputs.Workload(name="slab_plane_1x64x64_64", n=(1, 64, 64), nv=w.nv, L=(w.L[0] / 16, w.L[1], w.L[2]),
+                           vmin=w.vmin, vmax=w.vmax, G=w.G, bc=w.bc, dt=w.dt, steps=2, params=dict(w.params))
+
+
+def _king_coarse():
+    """The King W0 = 6 sphere of the 48^3 x 48^3 workload on 16^3 spatial cells
+    with the full 48^3 velocity grid (4.5e8 cells), isolated, a fixed step below
+    the workload's Courant step (0.047)"""
+    w = inputs.king_48_48()
+    return inputs.Workload(name="king_w6_16x48", n=(16,) * 3, nv=w.nv, L=w.L, vmin=w.vmin, vmax=w.vmax, G=w.G,
+                           bc=w.bc, dt=0.04, steps=2, params=dict(w.params))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("which", ["slab", "king"])
+def test_production_shape_sub_blocks_two_steps_match_oracle(which):
+    # sub-blocks of the two largest workloads, two steps each, FP64 and FP32
+    # against the oracle; the slab's density contrast is its field's rms, the
+    # King sphere's fields are not perturbative
+    w = _slab_plane() if which == "slab" else _king_coarse()
+    print("workload", w.name, w.shape, w.steps, flush=True)
+    _whole_run(w, w.steps, contrast=w.params["rms"] if which == "slab" else 1.0)
+
+
 # ---------------------------------------------------------------------------
 # fused passes at full size
 # ---------------------------------------------------------------------------
