@@ -10,10 +10,12 @@
                self term against the oracle and the cell's own integral.
   whole runs   FP64- and FP32-stored vp_run against the oracle's step of
                Eq. (17), from the same FP32-rounded input: the adjoint
-               workload's grid (16^3 x 24^3) for its 40 steps, and the
-               benchmark's grid (32^3 x 32^3) for 2 steps. FP64 within 1e-12
-               relative L1 in f, FP32 within 1e-5 with the mass drift within
-               1e-6 of the oracle's.
+               workload's grid (16^3 x 24^3) for its 40 steps, the
+               benchmark's grid (32^3 x 32^3) for 2 steps, and for 2 steps
+               sub-blocks of the slab (one x cell of its 64 x 64 planes with
+               the 64^3 velocity grid) and of the King sphere (16^3 x 48^3).
+               FP64 within 1e-12 relative L1 in f, FP32 within 1e-5 with the
+               mass drift within 1e-6 of the oracle's.
   fused passes the one-pass T_z T_y drift on the full-size workloads, sampled
                by velocity cell (a drift moves each velocity cell's spatial
                cube on its own) against the oracle's sweeps; vp_run's paired
